@@ -1,0 +1,277 @@
+"""Batched Newton-Raphson AC power flow on AMD MI355X (gfx950).
+
+Thin Python binding over the C ABI in ``include/pf.h``: argument marshalling only.
+Device memory and streams come from PyTorch; every step of the solve runs in the HIP
+library ``libpf_hip.so`` built from ``csrc/``.  Nothing here falls back to the CPU:
+if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpf_hip.so")
+
+PF_BUS_PQ, PF_BUS_PV, PF_BUS_REF = 1, 2, 3
+PF_ORDER_NATURAL, PF_ORDER_MIN_DEGREE, PF_ORDER_USER = 0, 1, 2
+PF_FP64, PF_FP32_LU = 0, 1
+PF_ST_CONVERGED, PF_ST_MAXITER, PF_ST_NONFINITE, PF_ST_PIVOT = 0, 1, 2, 3
+
+EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
+            "pf_workspace_bytes", "pf_solve_batch", "pf_eval_mismatch", "pf_eval_factor",
+            "pf_eval_step", "pf_plan_destroy", "pf_last_error"]
+
+
+class PfError(RuntimeError):
+    pass
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("n_bus", ctypes.c_int32), ("n_pv", ctypes.c_int32), ("n_pq", ctypes.c_int32),
+                ("n_unknowns", ctypes.c_int32), ("nnz_y", ctypes.c_int32), ("nnz_j", ctypes.c_int32),
+                ("nnz_lu", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("n_bs_levels", ctypes.c_int32), ("max_col", ctypes.c_int32),
+                ("n_updates", ctypes.c_int64), ("flops_refactor", ctypes.c_int64),
+                ("bytes_iter_fp64", ctypes.c_int64), ("bytes_iter_fp32", ctypes.c_int64)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("tile", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i8p = ctypes.POINTER(ctypes.c_int8)
+
+
+def lib():
+    """Load libpf_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PfError(f"HIP library not built: {LIB_PATH} is missing "
+                          "(run paper_2101_02270_amd.build.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        L.pf_analyze.argtypes = [ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _i8p, ctypes.c_int32,
+                                 _i32p, ctypes.POINTER(_vp)]
+        L.pf_plan_info.argtypes = [_vp, ctypes.POINTER(_PlanInfo)]
+        L.pf_plan_order.argtypes = [_vp, _i32p]
+        L.pf_plan_lu_pattern.argtypes = [_vp, _i32p, _i32p, _i32p]
+        L.pf_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_Opts)]
+        L.pf_workspace_bytes.restype = ctypes.c_size_t
+        L.pf_solve_batch.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp,
+                                     ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Opts), _vp,
+                                     ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
+        for f in ("pf_eval_mismatch",):
+            getattr(L, f).argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.POINTER(_Opts), _vp,
+                                      ctypes.c_size_t, _vp, _vp, _vp]
+        for f in ("pf_eval_factor", "pf_eval_step"):
+            getattr(L, f).argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.POINTER(_Opts), _vp,
+                                      ctypes.c_size_t, _vp, _vp]
+        L.pf_plan_destroy.argtypes = [_vp]
+        L.pf_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().pf_last_error().decode()
+        raise PfError(f"{what} failed ({rc}): {msg}")
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Plan:
+    """Analysed Ybus pattern (pf_analyze).  Device data live on the current device."""
+
+    def __init__(self, row_ptr, col_idx, bus_type, ordering: int = PF_ORDER_MIN_DEGREE,
+                 user_perm=None):
+        rp = _np(row_ptr, np.int32)
+        ci = _np(col_idx, np.int32)
+        bt = _np(bus_type, np.int8)
+        up = None if user_perm is None else _np(user_perm, np.int32)
+        h = _vp()
+        rc = lib().pf_analyze(int(rp.shape[0] - 1), int(ci.shape[0]),
+                              rp.ctypes.data_as(_i32p), ci.ctypes.data_as(_i32p),
+                              bt.ctypes.data_as(_i8p), int(ordering),
+                              up.ctypes.data_as(_i32p) if up is not None else None,
+                              ctypes.byref(h))
+        _check(rc, "pf_analyze")
+        self._h = h
+        info = _PlanInfo()
+        _check(lib().pf_plan_info(self._h, ctypes.byref(info)), "pf_plan_info")
+        self.info = {f: getattr(info, f) for f, _ in _PlanInfo._fields_}
+        self.n = self.info["n_bus"]
+        self.N = self.info["n_unknowns"]
+        self.nnz_y = self.info["nnz_y"]
+        self.nnz_lu = self.info["nnz_lu"]
+
+    @classmethod
+    def from_ybus(cls, yb, bus_type, **kw):
+        return cls(yb.row_ptr, yb.col_idx, bus_type, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def order(self) -> np.ndarray:
+        p = np.zeros(self.N, np.int32)
+        _check(lib().pf_plan_order(self._h, p.ctypes.data_as(_i32p)), "pf_plan_order")
+        return p
+
+    def lu_pattern(self):
+        cp = np.zeros(self.N + 1, np.int32)
+        ri = np.zeros(self.nnz_lu, np.int32)
+        lv = np.zeros(self.N, np.int32)
+        _check(lib().pf_plan_lu_pattern(self._h, cp.ctypes.data_as(_i32p), ri.ctypes.data_as(_i32p),
+                                        lv.ctypes.data_as(_i32p)), "pf_plan_lu_pattern")
+        return cp, ri, lv
+
+    def workspace_bytes(self, batch: int, precision=PF_FP64, tile=0, waves=0) -> int:
+        o = _Opts(precision, tile, waves)
+        return int(lib().pf_workspace_bytes(self._h, int(batch), ctypes.byref(o)))
+
+
+@dataclass
+class Result:
+    v: "object"          # torch float64 [B][n][2]
+    iters: "object"      # torch int32 [B]
+    converged: "object"  # torch uint8 [B]
+    status: "object"     # torch int8 [B]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, dtype, shape=None, name="tensor"):
+    torch = _torch()
+    if not t.is_cuda:
+        raise PfError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise PfError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise PfError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise PfError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return _vp(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _vp(s.cuda_stream)
+
+
+def _workspace(plan: Plan, batch, opts, workspace):
+    torch = _torch()
+    need = int(lib().pf_workspace_bytes(plan._h, int(batch), ctypes.byref(opts)))
+    if need == 0:
+        raise PfError("pf_workspace_bytes failed: " + lib().pf_last_error().decode())
+    if workspace is None or workspace.numel() * workspace.element_size() < need:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    ptr = workspace.data_ptr()
+    aligned = (ptr + 255) & ~255
+    avail = workspace.numel() * workspace.element_size() - (aligned - ptr)
+    return workspace, _vp(aligned), avail
+
+
+def _ybus_view(plan: Plan, ybus):
+    torch = _torch()
+    if ybus.dtype == torch.complex128:
+        ybus = torch.view_as_real(ybus)
+    return _dev_ptr(ybus, torch.float64, (plan.nnz_y, 2), "ybus"), ybus
+
+
+def _as_pairs(x, name):
+    torch = _torch()
+    if x.dtype == torch.complex128:
+        x = torch.view_as_real(x)
+    return x
+
+
+def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
+                precision: int = PF_FP64, tile: int = 0, waves: int = 0, workspace=None,
+                stream=None, out: Optional[Result] = None) -> Result:
+    """Run pf_solve_batch on device tensors: ybus complex128 [nnz_y], sbus complex128 [B][n],
+    v0 float64 [B][n][2].  Returns device tensors (valid once the stream synchronises)."""
+    torch = _torch()
+    B = int(v0.shape[0])
+    yp, _ = _ybus_view(plan, ybus)
+    s2 = _as_pairs(sbus, "sbus")
+    sp = _dev_ptr(s2, torch.float64, (B, plan.n, 2), "sbus")
+    vp = _dev_ptr(v0, torch.float64, (B, plan.n, 2), "v0")
+    if out is None:
+        out = Result(v=torch.empty((B, plan.n, 2), dtype=torch.float64, device=v0.device),
+                     iters=torch.empty(B, dtype=torch.int32, device=v0.device),
+                     converged=torch.empty(B, dtype=torch.uint8, device=v0.device),
+                     status=torch.empty(B, dtype=torch.int8, device=v0.device))
+    opts = _Opts(precision, tile, waves)
+    workspace, wp, avail = _workspace(plan, B, opts, workspace)
+    rc = lib().pf_solve_batch(plan._h, B, yp, 0, sp, vp, float(tol), int(max_iter), ctypes.byref(opts),
+                              wp, avail, _vp(out.v.data_ptr()), _vp(out.iters.data_ptr()),
+                              _vp(out.converged.data_ptr()), _vp(out.status.data_ptr()),
+                              _stream_ptr(stream))
+    _check(rc, "pf_solve_batch")
+    out._workspace = workspace
+    return out
+
+
+def _eval(fn, plan: Plan, ybus, sbus, v, out_shape, precision, tile, waves, extra_out=None,
+          workspace=None, stream=None):
+    torch = _torch()
+    B = int(v.shape[0])
+    yp, _ = _ybus_view(plan, ybus)
+    s2 = _as_pairs(sbus, "sbus")
+    sp = _dev_ptr(s2, torch.float64, (B, plan.n, 2), "sbus")
+    vp = _dev_ptr(v, torch.float64, (B, plan.n, 2), "v")
+    opts = _Opts(precision, tile, waves)
+    workspace, wp, avail = _workspace(plan, B, opts, workspace)
+    out = torch.empty(out_shape, dtype=torch.float64, device=v.device)
+    args = [plan._h, B, yp, sp, vp, ctypes.byref(opts), wp, avail, _vp(out.data_ptr())]
+    if extra_out is not None:
+        args.append(_vp(extra_out.data_ptr()))
+    args.append(_stream_ptr(stream))
+    _check(fn(*args), fn.__name__)
+    return out
+
+
+def eval_mismatch(plan: Plan, ybus, sbus, v, precision=PF_FP64, tile=0, waves=0, **kw):
+    """(F [B][N] in unknown order, max|F| [B]) at V."""
+    torch = _torch()
+    B = int(v.shape[0])
+    normf = torch.empty(B, dtype=torch.float64, device=v.device)
+    F = _eval(lib().pf_eval_mismatch, plan, ybus, sbus, v, (B, plan.N), precision, tile, waves,
+              extra_out=normf, **kw)
+    return F, normf
+
+
+def eval_factor(plan: Plan, ybus, sbus, v, precision=PF_FP64, tile=0, waves=0, **kw):
+    """Values of L+U-I [B][nnz_lu] of A = P J(V) P^T in lu_pattern() order."""
+    B = int(v.shape[0])
+    return _eval(lib().pf_eval_factor, plan, ybus, sbus, v, (B, plan.nnz_lu), precision, tile,
+                 waves, **kw)
+
+
+def eval_step(plan: Plan, ybus, sbus, v, precision=PF_FP64, tile=0, waves=0, **kw):
+    """Newton step dx [B][N] (unknown order) solving J(V) dx = F(V)."""
+    B = int(v.shape[0])
+    return _eval(lib().pf_eval_step, plan, ybus, sbus, v, (B, plan.N), precision, tile, waves, **kw)
