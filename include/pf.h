@@ -40,7 +40,10 @@ enum { PF_BUS_PQ = 1, PF_BUS_PV = 2, PF_BUS_REF = 3 };
 enum { PF_ORDER_NATURAL = 0, PF_ORDER_MIN_DEGREE = 1, PF_ORDER_USER = 2 };
 enum { PF_FP64 = 0, PF_FP32_LU = 1 };
 enum { PF_OK = 0, PF_EINVAL = -1, PF_ENOMEM = -2, PF_EDEVICE = -3, PF_ESTRUCT = -4 };
-enum { PF_ST_CONVERGED = 0, PF_ST_MAXITER = 1, PF_ST_NONFINITE = 2, PF_ST_PIVOT = 3 };
+/* Per-instance status.  PF_ST_INTERNAL: the kernel's bounded dataflow wait expired (a
+   library defect, never expected); the instance's result is invalid. */
+enum { PF_ST_CONVERGED = 0, PF_ST_MAXITER = 1, PF_ST_NONFINITE = 2, PF_ST_PIVOT = 3,
+       PF_ST_INTERNAL = -1 };
 
 /* Sizes of an analysed pattern. */
 typedef struct {

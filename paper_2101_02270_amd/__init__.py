@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libpf_hip.so")
 PF_BUS_PQ, PF_BUS_PV, PF_BUS_REF = 1, 2, 3
 PF_ORDER_NATURAL, PF_ORDER_MIN_DEGREE, PF_ORDER_USER = 0, 1, 2
 PF_FP64, PF_FP32_LU = 0, 1
-PF_ST_CONVERGED, PF_ST_MAXITER, PF_ST_NONFINITE, PF_ST_PIVOT = 0, 1, 2, 3
+PF_ST_CONVERGED, PF_ST_MAXITER, PF_ST_NONFINITE, PF_ST_PIVOT, PF_ST_INTERNAL = 0, 1, 2, 3, -1
 
 EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
             "pf_workspace_bytes", "pf_solve_batch", "pf_eval_mismatch", "pf_eval_factor",

@@ -9,17 +9,20 @@
 
 namespace pf {
 
-// Jacobian entry descriptor: (ybus_index << 2) | kind, or -1 for a fill slot.
-// kind bit 1: Q equation (else P); bit 0: derivative w.r.t. |V| (else angle).
-constexpr int kFill = -1;
+// Jacobian entry descriptor of one L+U-I slot: the Ybus entry p = (i, k) it derives
+// from, the buses i (equation) and k (unknown), and the kind: bit 1 = Q equation (else
+// P), bit 0 = derivative w.r.t. |V| (else angle).  p = -1 marks a fill slot.
+struct JacDesc {
+    int32_t p, i, k, kind;
+};
 
 // One column-to-column update of the left-looking refactorization: column j receives
-// LU(i, j) -= LU(k, j) * LU(i, k) for every i in the L part of column k.
+// LU(r, j) -= LU(k, j) * LU(r, k) for every r in the L part of column k.
 struct Update {
-    int32_t krel;   // position of row k inside column j (relative to the column start)
-    int32_t lbeg;   // absolute entry index of the first L entry of column k
-    int32_t lcnt;   // number of L entries of column k
-    int32_t roff;   // offset into rel[]: relative target positions in column j, one per L entry
+    int32_t krel_lcnt;  // position of row k inside column j | (number of L entries of k) << 16
+    int32_t lbeg;       // absolute entry index of the first L entry of column k
+    int32_t roff;       // offset into rel[]: relative target positions in column j
+    int32_t k;          // source column
 };
 
 // Everything pf_analyze derives from the pattern, on the host.
@@ -33,11 +36,10 @@ struct HostPlan {
     std::vector<int32_t> col_ptr;                 // N+1
     std::vector<int32_t> col_diag;                // N, relative position of the diagonal
     std::vector<int32_t> row_idx;                 // nnz_lu
-    std::vector<int32_t> desc;                    // nnz_lu Jacobian descriptors
+    std::vector<JacDesc> desc;                    // nnz_lu Jacobian descriptors
     // refactorization updates, per column j in ascending k
     std::vector<int32_t> upd_ptr;                 // N+1
     std::vector<Update> upd;
-    std::vector<int32_t> upd_k;                   // source column k of every update
     std::vector<int32_t> rel;                     // relative targets (one per multiply-add)
     // level schedules
     std::vector<int32_t> lev_ptr, lev_cols;       // refactorization levels (columns)
@@ -45,6 +47,9 @@ struct HostPlan {
     std::vector<int32_t> bs_lev_ptr, bs_lev_rows; // backward-substitution levels (rows)
     // backward substitution: for row j, the entries U(j, i), i > j
     std::vector<int32_t> bs_ptr, bs_pos, bs_col;
+    // panels: a PQ bus's angle and |V| columns (adjacent, same row list) form a 2-column
+    // supernode; every other column is a panel of its own
+    std::vector<int32_t> panel_ptr;               // first column of each panel, then N
     // right-hand side and update maps
     std::vector<int32_t> bus_peq, bus_qeq;        // bus -> position of its P / Q equation, -1
     std::vector<int32_t> pos_upd;                 // position j -> bus * 2 + (unknown is |V|)
@@ -57,12 +62,15 @@ struct DevPlan {
     int n, nnzy, N, nnzlu, n_levels, n_bs_levels, max_col, npvpq;
     const int32_t *yrp, *yci, *yrow;
     const int8_t *bus_type;
-    const int32_t *col_ptr, *col_diag, *desc;
-    const int32_t *upd_ptr, *rel, *upd_k;
+    const int32_t *col_ptr, *col_diag;
+    const JacDesc *desc;
+    const int32_t *upd_ptr, *rel;
     const Update *upd;
     const int32_t *lev_ptr, *lev_cols, *bs_lev_ptr, *bs_lev_rows;
     const int32_t *bs_ptr, *bs_pos, *bs_col;
     const int32_t *bus_peq, *bus_qeq, *pos_upd;
+    const int32_t *panel_ptr;
+    int n_panels;
 };
 
 struct Plan {

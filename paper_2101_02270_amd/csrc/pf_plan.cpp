@@ -210,6 +210,7 @@ int analyze(int n, int nnzy, const int32_t *row_ptr, const int32_t *col_idx,
         h.max_col = std::max(h.max_col, h.col_ptr[j + 1] - h.col_ptr[j]);
     }
     const int nnzlu = h.col_ptr[N];
+    if (h.max_col >= (1 << 16)) { err = "an LU column exceeds 65535 entries"; return PF_EINVAL; }
     h.row_idx.resize(nnzlu);
     for (int j = 0; j < N; j++) {
         int e = h.col_ptr[j];
@@ -231,10 +232,9 @@ int analyze(int n, int nnzy, const int32_t *row_ptr, const int32_t *col_idx,
             const int32_t *b0 = h.yci.data() + h.yrp[be], *b1 = h.yci.data() + h.yrp[be + 1];
             const int32_t *it = std::lower_bound(b0, b1, bc);
             if (it != b1 && *it == bc) {
-                int p = (int)(it - h.yci.data());
-                h.desc[e] = (p << 2) | (is_q << 1) | wrt_v;
+                h.desc[e] = JacDesc{(int32_t)(it - h.yci.data()), be, bc, (is_q << 1) | wrt_v};
             } else {
-                h.desc[e] = kFill;
+                h.desc[e] = JacDesc{-1, be, bc, 0};
             }
         }
     }
@@ -247,17 +247,17 @@ int analyze(int n, int nnzy, const int32_t *row_ptr, const int32_t *col_idx,
         for (int e = cs; e < h.col_ptr[j + 1]; e++) where[h.row_idx[e]] = e - cs;
         for (int k : Up[j]) {
             Update up;
-            up.krel = where[k];
+            const int lcnt = (int)L[k].size();
+            up.krel_lcnt = where[k] | (lcnt << 16);
             up.lbeg = h.col_ptr[k] + h.col_diag[k] + 1;
-            up.lcnt = (int)L[k].size();
             up.roff = (int)h.rel.size();
+            up.k = k;
             for (int i : L[k]) {
                 if (where[i] < 0) { err = "internal: symbolic pattern not closed"; return PF_EINVAL; }
                 h.rel.push_back(where[i]);
             }
             h.upd.push_back(up);
-            h.upd_k.push_back(k);
-            h.flops += up.lcnt;
+            h.flops += lcnt;
         }
         h.upd_ptr[j + 1] = (int)h.upd.size();
         for (int e = cs; e < h.col_ptr[j + 1]; e++) where[h.row_idx[e]] = -1;
@@ -309,6 +309,24 @@ int analyze(int n, int nnzy, const int32_t *row_ptr, const int32_t *col_idx,
         std::vector<int> fillp(h.bs_lev_ptr.begin(), h.bs_lev_ptr.end() - 1);
         for (int j = 0; j < N; j++) h.bs_lev_rows[fillp[blev[j]]++] = j;
     }
+
+    // ---- panels: (angle, |V|) pairs of one PQ bus with identical row lists
+    h.panel_ptr.clear();
+    for (int j = 0; j < N;) {
+        h.panel_ptr.push_back(j);
+        bool pair = false;
+        if (j + 1 < N) {
+            const int u0 = h.perm[j], u1 = h.perm[j + 1];
+            if (u0 < h.npvpq && u1 >= h.npvpq && h.ubus[u0] == h.ubus[u1]) {
+                const int n0 = h.col_ptr[j + 1] - h.col_ptr[j], n1 = h.col_ptr[j + 2] - h.col_ptr[j + 1];
+                pair = n0 == n1 && h.col_diag[j + 1] == h.col_diag[j] + 1 &&
+                       std::equal(h.row_idx.begin() + h.col_ptr[j], h.row_idx.begin() + h.col_ptr[j + 1],
+                                  h.row_idx.begin() + h.col_ptr[j + 1]);
+            }
+        }
+        j += pair ? 2 : 1;
+    }
+    h.panel_ptr.push_back(N);
 
     // ---- right-hand side and update maps
     h.bus_peq.assign(n, -1);

@@ -5,15 +5,19 @@
 //   M   mismatch S = V o conj(Y V) (Eq. 1), F = calculated - specified (Alg. 1), the
 //       per-instance infinity norm by wavefront shuffles and an LDS reduction, and the
 //       convergence / divergence decision;
-//   LU  level by level (Sec. 4.3.1), each wavefront takes a column j of A = P J P^T:
-//       it builds the Jacobian entries of the column straight from V and Ybus into an
-//       LDS working column (Sec. 3.1.2 "direct into permuted form A"), applies the
-//       left-looking updates from every finished column k with U(k,j) != 0 in ascending
-//       k (Alg. 2, the sparse VMAD with direct indexing of Alg. 3), carries the forward
-//       substitution of the right-hand side along (row j of L is read in the same
-//       pass), normalises the L part and writes the column back;
-//   BS  backward substitution by row levels, one wavefront per row, and the voltage
-//       update V <- V - dx for instances still iterating.
+//   LU  a sync-free dataflow form of the left-looking refactorization (Sec. 4.2-4.3):
+//       each wavefront takes the next column j of A = P J P^T from a counter, builds its
+//       Jacobian entries straight from V and Ybus into an LDS working column (Sec. 3.1.2,
+//       "direct into permuted form A"), applies the update of every column k with
+//       U(k,j) != 0 in ascending k (the sparse VMAD with direct indexing of Alg. 3) as
+//       soon as k is published, carries the forward substitution of the right-hand side
+//       along (row j of L is read in the same pass), normalises the L part, writes the
+//       column back and publishes it.  This generalises the paper's stage 2 (partial
+//       updates of unfinished columns) to every column: no level barriers remain, and
+//       the serial tail of the factorization pipelines across wavefronts;
+//   BS  backward substitution in the same dataflow style (row j waits for the rows
+//       i > j it reads), one wavefront per row, and the voltage update V <- V - dx for
+//       instances still iterating.
 // Each entry of every per-instance array is stored tile-interleaved: element e of
 // instance t of a tile lives at [e][t], so a wavefront reading entry e for the tile's
 // instances issues one contiguous T * sizeof(real) access (the paper's batched layout,
@@ -68,41 +72,62 @@ __device__ __forceinline__ void wave_sync()
 //   diagonal      dS_i/dangle_i = j (S_i - |V_i|^2 conj Y_ii),
 //                 dS_i/d|V_i|   = S_i / |V_i| + |V_i| conj Y_ii
 // P equations take the real part, Q equations the imaginary part.
-template <int T>
-__device__ __forceinline__ double jac_entry(int desc, int t, const int32_t *yrow, const int32_t *yci,
-                                            const double *ybus, const double *Vm, const double *Vr,
-                                            const double *Vi, const double *Ir, const double *Ii)
+// The column's own bus k supplies V_k, |V_k| and I_k (loaded once per panel); each
+// off-diagonal entry loads only V_i and Y_ik.  The angle and |V| columns of a PQ bus share
+// the entry's Ybus element and row, so one call yields both derivatives:
+//   angle:  off-diagonal -j w, diagonal j (S_k - |V_k|^2 conj Y_kk)
+//   |V|:    off-diagonal w / |V_k|, diagonal S_k / |V_k| + |V_k| conj Y_kk
+// with w = V_i conj(Y_ik V_k); P rows take the real part, Q rows the imaginary part.
+struct JacPair {
+    double th, vm;
+};
+
+__device__ __forceinline__ JacPair jac_entry(const JacDesc d, const double *ybus, const double2 *Vc_t,
+                                             double2 vk, double vmk, double2 ik)
 {
-    if (desc < 0) return 0.0;
-    const int p = desc >> 2, kind = desc & 3;
-    const int i = yrow[p], k = yci[p];
-    const double g = ybus[2 * p], bsus = ybus[2 * p + 1];
-    const double vri = Vr[i * T + t], vii = Vi[i * T + t];
-    double re, im;
-    if (i != k) {
-        const double vrk = Vr[k * T + t], vik = Vi[k * T + t];
-        const double cr = g * vrk - bsus * vik, ci = g * vik + bsus * vrk;      // Y_ik V_k
-        const double wr = vri * cr + vii * ci, wi = vii * cr - vri * ci;          // V_i conj(.)
-        if (kind & 1) {
-            const double inv = 1.0 / Vm[k * T + t];
-            re = wr * inv; im = wi * inv;
-        } else {
-            re = wi; im = -wr;
-        }
+    if (d.p < 0) return JacPair{0.0, 0.0};
+    const double2 y = reinterpret_cast<const double2 *>(ybus)[d.p];
+    double tr, ti, vr, vi;     // d/d angle and d/d|V| of S_i, complex
+    if (d.i != d.k) {
+        const double2 v = Vc_t[0];
+        const double cr = y.x * vk.x - y.y * vk.y, ci = y.x * vk.y + y.y * vk.x;     // Y_ik V_k
+        const double wr = v.x * cr + v.y * ci, wi = v.y * cr - v.x * ci;              // V_i conj(.)
+        tr = wi; ti = -wr;
+        const double inv = 1.0 / vmk;
+        vr = wr * inv; vi = wi * inv;
     } else {
-        const double ir = Ir[i * T + t], ii = Ii[i * T + t];
-        const double sr = vri * ir + vii * ii, si = vii * ir - vri * ii;          // S_i
-        const double vmi = Vm[i * T + t];
-        if (kind & 1) {
-            re = sr / vmi + vmi * g;
-            im = si / vmi - vmi * bsus;
-        } else {
-            const double m2 = vmi * vmi;
-            re = -si - m2 * bsus;
-            im = sr - m2 * g;
-        }
+        const double sr = vk.x * ik.x + vk.y * ik.y, si = vk.y * ik.x - vk.x * ik.y;  // S_k
+        const double m2 = vmk * vmk;
+        tr = -si - m2 * y.y; ti = sr - m2 * y.x;
+        vr = sr / vmk + vmk * y.x; vi = si / vmk - vmk * y.y;
     }
-    return (kind & 2) ? im : re;
+    const bool q = d.kind & 2;
+    return JacPair{q ? ti : tr, q ? vi : vr};
+}
+
+// Publication flags of the dataflow phases: one LDS byte per column (row).  A producer
+// makes its global writes visible to the workgroup (release fence) and then every lane of
+// the wavefront stores the same flag byte (plain stores, no atomics, so the loops stay free
+// of lane-divergent regions).  A consumer polls the byte uniformly across the wavefront
+// and acquires.  Every wait is bounded: a wait that exceeds the limit raises the tile's
+// error flag and stops waiting, so a wrong schedule can only produce wrong numbers and an
+// error status, never a hang.
+__device__ __forceinline__ void wait_published(unsigned char *flags, int j, int *err)
+{
+    for (unsigned spins = 0;; ++spins) {
+        const int f = __builtin_amdgcn_readfirstlane(
+            (int)__hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (f) break;
+        const int e = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (e) break;
+        if (spins >= (1u << 22)) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 template <typename R, int T, int NW>
@@ -117,7 +142,7 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
     __shared__ int s_bad[NW][T];
     __shared__ int s_active[T], s_status[T], s_iters[T], s_piv[T];
     __shared__ double s_normf[T];
-    __shared__ int s_any;
+    __shared__ int s_any, s_err;
 
     const DevPlan &P = a.p;
     const int tid = threadIdx.x;
@@ -137,11 +162,18 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
     R *Yv = reinterpret_cast<R *>(base + a.off_y);
     double *vec = reinterpret_cast<double *>(base + a.off_vec);
     const size_t nT = (size_t)n * T;
-    double *Vm = vec, *Va = vec + nT, *Vr = vec + 2 * nT, *Vi = vec + 3 * nT;
-    double *Ir = vec + 4 * nT, *Ii = vec + 5 * nT, *Ps = vec + 6 * nT, *Qs = vec + 7 * nT;
+    double *Vm = vec, *Va = vec + nT, *Ps = vec + 2 * nT, *Qs = vec + 3 * nT;
+    double2 *Vc = reinterpret_cast<double2 *>(vec + 4 * nT);     // V = |V| e^{j angle}
+    double2 *Ic = reinterpret_cast<double2 *>(vec + 6 * nT);     // I = Y V
 
-    R *xw = reinterpret_cast<R *>(smem_raw) + (size_t)wave * (P.max_col * T + T);
-    R *ysl = xw + (size_t)P.max_col * T;
+    // per wavefront: two working columns (a panel) and two right-hand-side slots
+    R *xw = reinterpret_cast<R *>(smem_raw) + (size_t)wave * 2 * (P.max_col * T + T);
+    R *xw1 = xw + (size_t)P.max_col * T;
+    R *ysl = xw1 + (size_t)P.max_col * T;
+    R *ysl1 = ysl + T;
+    unsigned char *done = reinterpret_cast<unsigned char *>(
+        reinterpret_cast<R *>(smem_raw) + (size_t)NW * 2 * (P.max_col * T + T));
+    int *err = &s_err;
 
     // ---- boundary layout [B][n][2] -> tile layout [n][T]
     for (int i = slot; i < n; i += SLOTS) {
@@ -159,6 +191,7 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
         s_status[t] = PF_ST_MAXITER;
         s_iters[t] = 0;
     }
+    if (tid == 0) s_err = 0;
     __syncthreads();
 
     for (int it = 0;; ++it) {
@@ -167,8 +200,7 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
             double sn, cs;
             const double vm = Vm[i * T + t];
             sincos(Va[i * T + t], &sn, &cs);
-            Vr[i * T + t] = vm * cs;
-            Vi[i * T + t] = vm * sn;
+            Vc[i * T + t] = make_double2(vm * cs, vm * sn);
         }
         __syncthreads();
         double mx = 0.0;
@@ -176,15 +208,14 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
         for (int i = slot; i < n; i += SLOTS) {
             double ir = 0.0, ii = 0.0;
             for (int q = P.yrp[i]; q < P.yrp[i + 1]; q++) {
-                const int k = P.yci[q];
-                const double g = a.ybus[2 * q], bs = a.ybus[2 * q + 1];
-                const double vr = Vr[k * T + t], vi = Vi[k * T + t];
-                ir += g * vr - bs * vi;
-                ii += g * vi + bs * vr;
+                const double2 y = reinterpret_cast<const double2 *>(a.ybus)[q];
+                const double2 v = Vc[P.yci[q] * T + t];
+                ir += y.x * v.x - y.y * v.y;
+                ii += y.x * v.y + y.y * v.x;
             }
-            Ir[i * T + t] = ir;
-            Ii[i * T + t] = ii;
-            const double vr = Vr[i * T + t], vi = Vi[i * T + t];
+            Ic[i * T + t] = make_double2(ir, ii);
+            const double2 vv = Vc[i * T + t];
+            const double vr = vv.x, vi = vv.y;
             const int pe = P.bus_peq[i], qe = P.bus_qeq[i];
             if (pe >= 0) {
                 const double f = (vr * ir + vi * ii) - Ps[i * T + t];
@@ -236,40 +267,83 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
         }
 
         // ============================ LU: Jacobian -> refactorization -> forward substitution
-        for (int lv = 0; lv < P.n_levels; lv++) {
-            const int c1 = P.lev_ptr[lv + 1];
-            for (int c = P.lev_ptr[lv] + wave; c < c1; c += NW) {
-                const int j = P.lev_cols[c];
-                const int cs = P.col_ptr[j];
-                const int cnt = P.col_ptr[j + 1] - cs;
-                const int dr = P.col_diag[j];
-                for (int e = s; e < cnt; e += SL)
-                    xw[e * T + t] = (R)jac_entry<T>(P.desc[cs + e], t, P.yrow, P.yci, a.ybus, Vm, Vr, Vi, Ir, Ii);
-                if (s == 0) ysl[t] = Yv[j * T + t];
-                wave_sync();
-                const int u1 = P.upd_ptr[j + 1];
-                for (int u = P.upd_ptr[j]; u < u1; u++) {
-                    const Update up = P.upd[u];
-                    const int k = P.upd_k[u];
-                    const R m = xw[up.krel * T + t];
-                    for (int r = s; r < up.lcnt; r += SL) {
-                        const R l = LU[(size_t)(up.lbeg + r) * T + t];
-                        const int tr = P.rel[up.roff + r];
-                        xw[tr * T + t] = fma(-m, l, xw[tr * T + t]);
-                        if (tr == dr) ysl[t] = fma(-l, Yv[k * T + t], ysl[t]);
-                    }
-                    wave_sync();
+        for (int w = tid; w < N; w += NT)
+            __hip_atomic_store(&done[w], (unsigned char)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __syncthreads();
+        // Panels (one column, or the angle/|V| pair of a PQ bus sharing one row list) in
+        // elimination order, round-robin over the wavefronts: the smallest unfinished panel
+        // always has every source published, so some wavefront always makes progress.
+        for (int pi = wave; pi < P.n_panels; pi += NW) {
+            const int j = P.panel_ptr[pi];
+            const bool two = P.panel_ptr[pi + 1] - j == 2;
+            const int cs = P.col_ptr[j];
+            const int cnt = P.col_ptr[j + 1] - cs;
+            const int dr = P.col_diag[j];
+            {
+                const int kb = P.pos_upd[j] >> 1;      // bus of the panel's unknowns
+                const double2 vk = Vc[kb * T + t], ik = Ic[kb * T + t];
+                const double vmk = Vm[kb * T + t];
+                for (int e = s; e < cnt; e += SL) {
+                    const JacDesc d0 = P.desc[cs + e];
+                    const JacPair jp = jac_entry(d0, a.ybus, Vc + d0.i * T + t, vk, vmk, ik);
+                    xw[e * T + t] = (R)((d0.kind & 1) ? jp.vm : jp.th);
+                    if (two) xw1[e * T + t] = (R)jp.vm;
                 }
-                const R d = xw[dr * T + t];
-                if (s == 0 && valid && !(fabs((double)d) > 1e-300 && isfinite((double)d))) s_piv[t] = 1;
-                for (int e = dr + 1 + s; e < cnt; e += SL) xw[e * T + t] = xw[e * T + t] / d;
+            }
+            if (s == 0) {
+                ysl[t] = Yv[j * T + t];
+                if (two) ysl1[t] = Yv[(j + 1) * T + t];
+            }
+            const int u0 = P.upd_ptr[j], u1 = P.upd_ptr[j + 1];
+            Update upn{};
+            if (u0 < u1) upn = P.upd[u0];
+            for (int u = u0; u < u1; u++) {
+                const Update up = upn;
+                if (u + 1 < u1) upn = P.upd[u + 1];     // next descriptor in flight meanwhile
+                const int krel = up.krel_lcnt & 0xffff, lcnt = up.krel_lcnt >> 16;
+                wait_published(done, up.k, err);
                 wave_sync();
-                for (int e = s; e < cnt; e += SL) LU[(size_t)(cs + e) * T + t] = xw[e * T + t];
-                if (s == 0) Yv[j * T + t] = ysl[t];
+                const R m0 = xw[krel * T + t];
+                const R m1 = two ? xw1[krel * T + t] : (R)0;
+                for (int r = s; r < lcnt; r += SL) {
+                    const R l = LU[(size_t)(up.lbeg + r) * T + t];
+                    const int tr = P.rel[up.roff + r];
+                    xw[tr * T + t] = fma(-m0, l, xw[tr * T + t]);
+                    if (two) xw1[tr * T + t] = fma(-m1, l, xw1[tr * T + t]);
+                    if (tr == dr) ysl[t] = fma(-l, Yv[up.k * T + t], ysl[t]);
+                    else if (two && tr == dr + 1) ysl1[t] = fma(-l, Yv[up.k * T + t], ysl1[t]);
+                }
+            }
+            wave_sync();
+            const R d = xw[dr * T + t];
+            if (s == 0 && valid && !(fabs((double)d) > 1e-300 && isfinite((double)d))) s_piv[t] = 1;
+            for (int e = dr + 1 + s; e < cnt; e += SL) xw[e * T + t] = xw[e * T + t] / d;
+            wave_sync();
+            if (two) {
+                // the pair's second column receives the update of the first (its last source)
+                const R m = xw1[dr * T + t];
+                for (int e = dr + 1 + s; e < cnt; e += SL) xw1[e * T + t] = fma(-m, xw[e * T + t], xw1[e * T + t]);
+                wave_sync();
+                if (s == 0) ysl1[t] = fma(-xw[(dr + 1) * T + t], ysl[t], ysl1[t]);
+                const R d1 = xw1[(dr + 1) * T + t];
+                if (s == 0 && valid && !(fabs((double)d1) > 1e-300 && isfinite((double)d1))) s_piv[t] = 1;
+                for (int e = dr + 2 + s; e < cnt; e += SL) xw1[e * T + t] = xw1[e * T + t] / d1;
                 wave_sync();
             }
-            __syncthreads();
+            for (int e = s; e < cnt; e += SL) {
+                LU[(size_t)(cs + e) * T + t] = xw[e * T + t];
+                if (two) LU[(size_t)(cs + cnt + e) * T + t] = xw1[e * T + t];
+            }
+            if (s == 0) {
+                Yv[j * T + t] = ysl[t];
+                if (two) Yv[(j + 1) * T + t] = ysl1[t];
+            }
+            wave_sync();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __hip_atomic_store(&done[j], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (two) __hip_atomic_store(&done[j + 1], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+        __syncthreads();
         if (tid < T && s_piv[t] && s_active[t] && a.mode == MODE_SOLVE) {
             s_status[t] = PF_ST_PIVOT; s_active[t] = 0; s_iters[t] = it;
         }
@@ -279,33 +353,61 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
                 for (size_t e = slot; e < nnz; e += SLOTS) a.aux_out[(size_t)b * nnz + e] = (double)LU[e * T + t];
             return;
         }
+        for (int w = tid; w < N; w += NT)
+            __hip_atomic_store(&done[w], (unsigned char)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __syncthreads();
 
         // ============================ BS: backward substitution and voltage update
+        // Panels in reverse elimination order.  For a pair (j, j+1) the rows share their
+        // column set i > j+1, and U(j, i), U(j+1, i) sit next to each other in column i.
         const bool upd_v = (a.mode == MODE_SOLVE);
-        for (int lv = 0; lv < P.n_bs_levels; lv++) {
-            const int r1 = P.bs_lev_ptr[lv + 1];
-            for (int r = P.bs_lev_ptr[lv] + wave; r < r1; r += NW) {
-                const int j = P.bs_lev_rows[r];
-                R acc = 0;
-                const int q1 = P.bs_ptr[j + 1];
-                for (int q = P.bs_ptr[j] + s; q < q1; q += SL)
-                    acc = fma(LU[(size_t)P.bs_pos[q] * T + t], Yv[P.bs_col[q] * T + t], acc);
-#pragma unroll
-                for (int off = T; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
-                if (s == 0) {
-                    const R z = (Yv[j * T + t] - acc) / LU[(size_t)(P.col_ptr[j] + P.col_diag[j]) * T + t];
-                    Yv[j * T + t] = z;
-                    if (upd_v && s_active[t]) {
-                        const int pu = P.pos_upd[j];
-                        const int bus = pu >> 1;
-                        if (pu & 1) Vm[bus * T + t] -= (double)z;
-                        else Va[bus * T + t] -= (double)z;
-                    }
+        for (int pi = P.n_panels - 1 - wave; pi >= 0; pi -= NW) {
+            const int j = P.panel_ptr[pi];
+            const bool two = P.panel_ptr[pi + 1] - j == 2;
+            const int jl = two ? j + 1 : j;            // the panel's last row
+            R acc0 = 0, acc1 = 0;
+            const int q0 = P.bs_ptr[jl], q1 = P.bs_ptr[jl + 1];
+            for (int q = q0; q < q1; q++) wait_published(done, P.bs_col[q], err);
+            for (int q = q0 + s; q < q1; q += SL) {
+                const R z = Yv[P.bs_col[q] * T + t];
+                const size_t pq = (size_t)P.bs_pos[q];
+                if (two) {
+                    acc1 = fma(LU[pq * T + t], z, acc1);
+                    acc0 = fma(LU[(pq - 1) * T + t], z, acc0);
+                } else {
+                    acc0 = fma(LU[pq * T + t], z, acc0);
                 }
             }
-            __syncthreads();
+#pragma unroll
+            for (int off = T; off < 64; off <<= 1) {
+                acc0 += __shfl_xor(acc0, off);
+                acc1 += __shfl_xor(acc1, off);
+            }
+            if (s == 0) {
+                const int cs = P.col_ptr[j], dr = P.col_diag[j];
+                R zl = 0;
+                if (two) {
+                    const int cs1 = P.col_ptr[j + 1];
+                    zl = (Yv[(j + 1) * T + t] - acc1) / LU[(size_t)(cs1 + dr + 1) * T + t];
+                    Yv[(j + 1) * T + t] = zl;
+                    acc0 = fma(LU[(size_t)(cs1 + dr) * T + t], zl, acc0);
+                }
+                const R z0 = (Yv[j * T + t] - acc0) / LU[(size_t)(cs + dr) * T + t];
+                Yv[j * T + t] = z0;
+                if (upd_v && s_active[t]) {
+                    const int pu = P.pos_upd[j];
+                    const int bus = pu >> 1;
+                    if (pu & 1) Vm[bus * T + t] -= (double)z0;
+                    else Va[bus * T + t] -= (double)z0;
+                    if (two) Vm[bus * T + t] -= (double)zl;
+                }
+            }
+            wave_sync();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __hip_atomic_store(&done[j], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (two) __hip_atomic_store(&done[j + 1], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+        __syncthreads();
         if (a.mode == MODE_STEP) {
             if (valid)
                 for (int j = slot; j < N; j += SLOTS) a.aux_out[(size_t)b * N + a.perm[j]] = (double)Yv[j * T + t];
@@ -321,9 +423,10 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
             a.v_out[o + 1] = Va[i * T + t];
         }
         if (s == 0 && wave == 0) {
+            const int st = s_err ? PF_ST_INTERNAL : s_status[t];
             a.iters_out[b] = s_iters[t];
-            a.conv_out[b] = s_status[t] == PF_ST_CONVERGED ? 1 : 0;
-            if (a.status_out) a.status_out[b] = (int8_t)s_status[t];
+            a.conv_out[b] = st == PF_ST_CONVERGED ? 1 : 0;
+            if (a.status_out) a.status_out[b] = (int8_t)st;
         }
     }
 }
@@ -352,22 +455,36 @@ static TileLayout tile_layout(const HostPlan &h, const Config &c)
 static size_t lds_bytes(const HostPlan &h, const Config &c)
 {
     const size_t rs = c.precision == PF_FP32_LU ? 4 : 8;
-    return (size_t)c.waves * ((size_t)h.max_col * c.tile + c.tile) * rs;
+    return (size_t)c.waves * 2 * ((size_t)h.max_col * c.tile + c.tile) * rs + (size_t)h.N;
 }
 
+static size_t lds_bytes(const HostPlan &h, const Config &c);
+static constexpr size_t kLdsLimit = 160 * 1024 - 8192;
+
+// Explicit tile/waves are validated; zeros pick the first candidate whose working columns
+// fit in LDS (larger tiles first: wider coalesced rows and fewer workgroups).
 static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c, std::string &err)
 {
     c.precision = o ? o->precision : PF_FP64;
-    c.tile = o ? o->tile : 0;
-    c.waves = o ? o->waves : 0;
+    const int tile = o ? o->tile : 0, waves = o ? o->waves : 0;
     if (c.precision != PF_FP64 && c.precision != PF_FP32_LU) { err = "unknown precision"; return false; }
-    if (c.tile == 0) c.tile = c.precision == PF_FP64 ? 16 : 32;
-    if (c.waves == 0) c.waves = 4;
-    const bool ok_tile = c.precision == PF_FP64 ? (c.tile == 8 || c.tile == 16) : (c.tile == 16 || c.tile == 32);
-    if (!ok_tile) { err = "unsupported tile size for this precision"; return false; }
-    if (c.waves != 2 && c.waves != 4 && c.waves != 8) { err = "waves must be 2, 4 or 8"; return false; }
-    (void)h;
-    return true;
+    const bool fp64 = c.precision == PF_FP64;
+    if (tile != 0 && !(fp64 ? (tile == 4 || tile == 8 || tile == 16) : (tile == 8 || tile == 16 || tile == 32))) {
+        err = "unsupported tile size for this precision"; return false;
+    }
+    if (waves != 0 && waves != 2 && waves != 4 && waves != 8 && waves != 16) {
+        err = "waves must be 2, 4, 8 or 16"; return false;
+    }
+    static const int cand64[][2] = {{8, 4}, {4, 8}, {8, 2}, {4, 4}, {4, 2}};
+    static const int cand32[][2] = {{16, 4}, {8, 8}, {16, 2}, {8, 4}, {8, 2}};
+    for (const auto &cw : (fp64 ? cand64 : cand32)) {
+        c.tile = tile ? tile : cw[0];
+        c.waves = waves ? waves : cw[1];
+        if (lds_bytes(h, c) <= kLdsLimit) return true;
+    }
+    err = "the longest LU column (" + std::to_string(h.max_col) + " entries) does not fit in LDS for any "
+          "supported tile/wave configuration";
+    return false;
 }
 
 template <typename R, int T, int NW>
@@ -391,15 +508,18 @@ static hipError_t launch_t(const KArgs &a, int grid, size_t lds, hipStream_t st)
     switch (c.waves) {                                                         \
     case 2: return launch_t<R, T, 2>(a, grid, lds, st);                        \
     case 4: return launch_t<R, T, 4>(a, grid, lds, st);                        \
-    default: return launch_t<R, T, 8>(a, grid, lds, st);                       \
+    case 8: return launch_t<R, T, 8>(a, grid, lds, st);                        \
+    default: return launch_t<R, T, 16>(a, grid, lds, st);                      \
     }
 
 static hipError_t launch(const Config &c, const KArgs &a, int grid, size_t lds, hipStream_t st)
 {
     if (c.precision == PF_FP64) {
+        if (c.tile == 4) { PF_DISPATCH_NW(double, 4) }
         if (c.tile == 8) { PF_DISPATCH_NW(double, 8) }
         PF_DISPATCH_NW(double, 16)
     } else {
+        if (c.tile == 8) { PF_DISPATCH_NW(float, 8) }
         if (c.tile == 16) { PF_DISPATCH_NW(float, 16) }
         PF_DISPATCH_NW(float, 32)
     }
@@ -434,7 +554,7 @@ static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *
     }
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) { set_error("workspace must be 256-byte aligned"); return PF_EINVAL; }
     const size_t lds = lds_bytes(h, c);
-    if (lds > 160 * 1024 - 8192) {
+    if (lds > kLdsLimit) {
         set_error("longest LU column needs " + std::to_string(lds) + " B of LDS; use a smaller tile or fewer waves");
         return PF_EINVAL;
     }
@@ -482,21 +602,21 @@ static int upload(Plan *pl)
     const size_t o_yrp = off.add(h.yrp), o_yci = off.add(h.yci), o_yrow = off.add(h.yrow);
     const size_t o_bt = off.add(h.bus_type), o_cp = off.add(h.col_ptr), o_cd = off.add(h.col_diag);
     const size_t o_desc = off.add(h.desc), o_up = off.add(h.upd_ptr), o_rel = off.add(h.rel);
-    const size_t o_uk = off.add(h.upd_k), o_upd = off.add(h.upd), o_lp = off.add(h.lev_ptr);
+    const size_t o_upd = off.add(h.upd), o_lp = off.add(h.lev_ptr);
     const size_t o_lc = off.add(h.lev_cols), o_blp = off.add(h.bs_lev_ptr), o_blr = off.add(h.bs_lev_rows);
     const size_t o_bp = off.add(h.bs_ptr), o_bpos = off.add(h.bs_pos), o_bcol = off.add(h.bs_col);
     const size_t o_pe = off.add(h.bus_peq), o_qe = off.add(h.bus_qeq), o_pu = off.add(h.pos_upd);
-    const size_t o_perm = off.add(h.perm);
+    const size_t o_perm = off.add(h.perm), o_pp = off.add(h.panel_ptr);
     std::vector<char> host(off.bytes, 0);
     auto put = [&](size_t o, const auto &v) {
         if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * sizeof(v[0]));
     };
     put(o_yrp, h.yrp); put(o_yci, h.yci); put(o_yrow, h.yrow); put(o_bt, h.bus_type);
     put(o_cp, h.col_ptr); put(o_cd, h.col_diag); put(o_desc, h.desc); put(o_up, h.upd_ptr);
-    put(o_rel, h.rel); put(o_uk, h.upd_k); put(o_upd, h.upd); put(o_lp, h.lev_ptr);
+    put(o_rel, h.rel); put(o_upd, h.upd); put(o_lp, h.lev_ptr);
     put(o_lc, h.lev_cols); put(o_blp, h.bs_lev_ptr); put(o_blr, h.bs_lev_rows); put(o_bp, h.bs_ptr);
     put(o_bpos, h.bs_pos); put(o_bcol, h.bs_col); put(o_pe, h.bus_peq); put(o_qe, h.bus_qeq);
-    put(o_pu, h.pos_upd); put(o_perm, h.perm);
+    put(o_pu, h.pos_upd); put(o_perm, h.perm); put(o_pp, h.panel_ptr);
     void *dm = nullptr;
     if (hipMalloc(&dm, off.bytes) != hipSuccess) { set_error("hipMalloc of the plan failed"); return PF_ENOMEM; }
     if (hipMemcpy(dm, host.data(), off.bytes, hipMemcpyHostToDevice) != hipSuccess) {
@@ -513,14 +633,16 @@ static int upload(Plan *pl)
     d.max_col = h.max_col; d.npvpq = h.npvpq;
     d.yrp = (const int32_t *)(D + o_yrp); d.yci = (const int32_t *)(D + o_yci); d.yrow = (const int32_t *)(D + o_yrow);
     d.bus_type = (const int8_t *)(D + o_bt);
-    d.col_ptr = (const int32_t *)(D + o_cp); d.col_diag = (const int32_t *)(D + o_cd); d.desc = (const int32_t *)(D + o_desc);
-    d.upd_ptr = (const int32_t *)(D + o_up); d.rel = (const int32_t *)(D + o_rel); d.upd_k = (const int32_t *)(D + o_uk);
+    d.col_ptr = (const int32_t *)(D + o_cp); d.col_diag = (const int32_t *)(D + o_cd); d.desc = (const JacDesc *)(D + o_desc);
+    d.upd_ptr = (const int32_t *)(D + o_up); d.rel = (const int32_t *)(D + o_rel);
     d.upd = (const Update *)(D + o_upd);
     d.lev_ptr = (const int32_t *)(D + o_lp); d.lev_cols = (const int32_t *)(D + o_lc);
     d.bs_lev_ptr = (const int32_t *)(D + o_blp); d.bs_lev_rows = (const int32_t *)(D + o_blr);
     d.bs_ptr = (const int32_t *)(D + o_bp); d.bs_pos = (const int32_t *)(D + o_bpos); d.bs_col = (const int32_t *)(D + o_bcol);
     d.bus_peq = (const int32_t *)(D + o_pe); d.bus_qeq = (const int32_t *)(D + o_qe); d.pos_upd = (const int32_t *)(D + o_pu);
     pl->perm_dev = (const int32_t *)(D + o_perm);
+    d.panel_ptr = (const int32_t *)(D + o_pp);
+    d.n_panels = (int)h.panel_ptr.size() - 1;
     return PF_OK;
 }
 

@@ -1,0 +1,163 @@
+"""Host-side checks of the C-ABI library (no GPU needed): every declared symbol is
+exported, pf_analyze rejects malformed patterns, and the plan's symbolic analysis is the
+structure the numerical kernels rely on.
+
+Symbolic pins (independent of the plan's own code):
+  * the L+U pattern equals the nonzero structure of a dense LU without pivoting of
+    P J P^T with random values (brute force on small grids);
+  * every column dependency k -> j (U(k, j) != 0) has level(k) < level(j);
+  * the elimination order is a permutation and keeps a PQ bus's two unknowns adjacent;
+  * the minimum-degree order produces much less fill than the natural order.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gridgen as gg
+import oracle
+import paper_2101_02270_amd as pf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "pf_analyze" in names and "pf_solve_batch" in names
+    lib = ctypes.CDLL(pf.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(pf.EXPORTED)
+
+
+def _pattern(g):
+    yb = gg.ybus(g)
+    return yb.row_ptr.copy(), yb.col_idx.copy(), g.bus_type.copy()
+
+
+def _analyze_rc(rp, ci, bt, ordering=pf.PF_ORDER_MIN_DEGREE, perm=None):
+    try:
+        pf.Plan(rp, ci, bt, ordering=ordering, user_perm=perm)
+        return 0, ""
+    except pf.PfError as e:
+        return -1, str(e)
+
+
+def test_analyze_rejects_malformed_input():
+    g = gg.grid("c0_14bus")
+    rp, ci, bt = _pattern(g)
+    assert _analyze_rc(rp, ci, bt)[0] == 0
+    b2 = bt.copy(); b2[b2 == gg.REF] = gg.PQ
+    assert "REF" in _analyze_rc(rp, ci, b2)[1]
+    b3 = bt.copy(); b3[3] = gg.REF
+    assert "REF" in _analyze_rc(rp, ci, b3)[1]
+    b4 = bt.copy(); b4[2] = 7
+    assert "type" in _analyze_rc(rp, ci, b4)[1]
+    # drop the diagonal of row 5
+    r5 = list(range(rp[5], rp[6]))
+    d = [p for p in r5 if ci[p] == 5][0]
+    ci2 = np.delete(ci, d); rp2 = rp.copy(); rp2[6:] -= 1
+    assert "diagonal" in _analyze_rc(rp2, ci2, bt)[1]
+    # unsorted columns in row 4
+    ci3 = ci.copy(); a, b_ = rp[4], rp[5]
+    ci3[a:b_] = ci3[a:b_][::-1]
+    assert "unsorted" in _analyze_rc(rp, ci3, bt)[1]
+    # structural asymmetry: remove one off-diagonal (i, k) but keep (k, i)
+    i = 6
+    off = [p for p in range(rp[i], rp[i + 1]) if ci[p] != i][0]
+    ci4 = np.delete(ci, off); rp4 = rp.copy(); rp4[i + 1:] -= 1
+    assert "symmetric" in _analyze_rc(rp4, ci4, bt)[1]
+    # bad user permutation
+    N = (bt == gg.PV).sum() + 2 * (bt == gg.PQ).sum()
+    bad = np.arange(N); bad[0] = 1
+    assert "permutation" in _analyze_rc(rp, ci, bt, pf.PF_ORDER_USER, bad)[1]
+
+
+def test_isolated_bus_rejected_and_single_bus_accepted():
+    rp = np.array([0, 1, 3, 5], np.int32)
+    ci = np.array([0, 1, 2, 1, 2], np.int32)
+    bt = np.array([gg.PQ, gg.REF, gg.PQ], np.int8)
+    assert "isolated" in _analyze_rc(rp, ci, bt)[1]
+    p = pf.Plan(np.array([0, 1], np.int32), np.array([0], np.int32), np.array([gg.REF], np.int8))
+    assert p.N == 0 and p.nnz_lu == 0
+
+
+def dense_symbolic(osys, perm):
+    """Nonzero structure of a dense no-pivot LU of P J P^T with random values."""
+    rp, ci = osys.jacobian_pattern()
+    N = osys.N
+    A = np.zeros((N, N))
+    rng = np.random.default_rng(0)
+    for r in range(N):
+        A[r, ci[rp[r]:rp[r + 1]]] = rng.uniform(1, 2, rp[r + 1] - rp[r])
+    A += np.eye(N) * N * 4               # keep the elimination well defined
+    A = A[np.ix_(perm, perm)]
+    S = A != 0
+    for k in range(N):
+        rows = np.flatnonzero(S[k + 1:, k]) + k + 1
+        cols = np.flatnonzero(S[k, k + 1:]) + k + 1
+        S[np.ix_(rows, cols)] = True
+    return S
+
+
+@pytest.mark.parametrize("name", ["c0_14bus", "c4_100bus"])
+@pytest.mark.parametrize("ordering", [pf.PF_ORDER_MIN_DEGREE, pf.PF_ORDER_NATURAL])
+def test_symbolic_pattern_matches_dense_elimination(name, ordering):
+    g = gg.grid(name)
+    yb = gg.ybus(g)
+    plan = pf.Plan.from_ybus(yb, g.bus_type, ordering=ordering)
+    osys = oracle.System.from_ybus(yb, g.bus_type)
+    perm = plan.order()
+    assert sorted(perm.tolist()) == list(range(plan.N))
+    cp, ri, lv = plan.lu_pattern()
+    S = np.zeros((plan.N, plan.N), bool)
+    for j in range(plan.N):
+        rows = ri[cp[j]:cp[j + 1]]
+        assert np.all(np.diff(rows) > 0) and j in rows
+        S[rows, j] = True
+    assert np.array_equal(S, dense_symbolic(osys, perm))
+    assert plan.nnz_lu >= plan.info["nnz_j"]
+    # level validity: every dependency U(k, j) != 0, k < j has level(k) < level(j)
+    for j in range(plan.N):
+        for k in ri[cp[j]:cp[j + 1]]:
+            if k < j:
+                assert lv[k] < lv[j]
+    assert plan.info["n_levels"] == lv.max() + 1
+
+
+def test_min_degree_pairs_and_fill():
+    g = gg.grid("c1_1350bus")
+    yb = gg.ybus(g)
+    md = pf.Plan.from_ybus(yb, g.bus_type)
+    nat = pf.Plan.from_ybus(yb, g.bus_type, ordering=pf.PF_ORDER_NATURAL)
+    assert md.nnz_lu < 0.25 * nat.nnz_lu
+    perm = md.order()
+    npvpq = int((g.bus_type != gg.REF).sum())
+    pv, pq = np.flatnonzero(g.bus_type == gg.PV), np.flatnonzero(g.bus_type == gg.PQ)
+    ubus = np.r_[pv, pq, pq]
+    pos = np.empty_like(perm); pos[perm] = np.arange(perm.size)
+    # the |V| unknown of every PQ bus sits right after its angle
+    for k, bus in enumerate(pq):
+        assert pos[npvpq + k] == pos[len(pv) + k] + 1
+    assert ubus[perm[0]] in np.r_[pv, pq]
+
+
+def test_plan_info_and_workspace():
+    g = gg.grid("c1_1350bus")
+    plan = pf.Plan.from_ybus(gg.ybus(g), g.bus_type)
+    info = plan.info
+    assert info["n_bus"] == g.n and info["n_unknowns"] == info["n_pv"] + 2 * info["n_pq"]
+    assert info["flops_refactor"] > info["nnz_lu"]
+    assert info["bytes_iter_fp32"] < info["bytes_iter_fp64"]
+    w64 = plan.workspace_bytes(10000)
+    w32 = plan.workspace_bytes(10000, precision=pf.PF_FP32_LU)
+    assert w64 > 10000 * info["nnz_lu"] * 8 and 0 < w32 < w64
+    assert plan.workspace_bytes(10000, tile=7) == 0
