@@ -62,6 +62,143 @@ def cpu_baseline(g, yb, sc, tol, max_iter, target_s=15.0):
                       f"order, pivoting left-looking LU), {cores} threads, {dt:.1f} s"}
 
 
+def timed_solves(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
+def warm_start_variants(steps, warmup, epochs, log):
+    """Train the warm-start network on the 50,000-scenario training set of the 1,350-bus
+    grid (solved by the FP64 GPU path), then time FP64 and FP32-LU solves of the 10,000
+    held-out scenarios from flat start and from the network's start.  Network inference
+    and the flat-start re-solve of failures are inside the timed region."""
+    import torch
+    import gridgen as gg
+    import paper_2101_02270_amd as pf
+    from paper_2101_02270_amd import warmstart as ws
+    dev = torch.device("cuda", 0)
+    (g, yb, tr), = gg.workload("c3_train")
+    (_, _, ev), = gg.workload("c3_eval")
+    plan = pf.Plan.from_ybus(yb, g.bus_type)
+    y = torch.from_numpy(yb.val).to(dev)
+    t0 = time.perf_counter()
+    sols, oks = [], []
+    for b0 in range(0, tr.batch, 10000):
+        s = torch.from_numpy(tr.sbus[b0:b0 + 10000]).to(dev)
+        v = torch.from_numpy(tr.v0[b0:b0 + 10000]).to(dev)
+        r = pf.solve_batch(plan, y, s, v)
+        sols.append(r.v.cpu().numpy()); oks.append(r.converged.cpu().numpy().astype(bool))
+    vsol = np.concatenate(sols); ok = np.concatenate(oks)
+    net = ws.WarmStartNet(g.bus_type, hidden=(512, 512, 512), seed=0)
+    mu_x, sd_x = ws.feature_stats(net, tr.sbus[ok], tr.v0[ok])
+    Y = ws.targets_from_solution(net, vsol[ok])
+    mu_y, sd_y = ws.target_stats(Y)
+    net.set_normalization(mu_x, sd_x, mu_y, sd_y)
+    idx = np.flatnonzero(ok)
+    X = torch.empty((idx.size, net.dims[0]), dtype=torch.int16, device=dev)
+    for b0 in range(0, idx.size, 10000):
+        sel = idx[b0:b0 + 10000]
+        X[b0:b0 + sel.size] = net.features(torch.from_numpy(tr.sbus[sel]).to(dev), torch.from_numpy(tr.v0[sel]).to(dev))
+    Yn = torch.from_numpy(((Y - mu_y) / sd_y).astype(np.float32)).to(dev)
+    del sols
+    prep_s = time.perf_counter() - t0
+    n_train = int(0.9 * idx.size)
+    rep = net.fit(X, Yn, n_train, epochs=epochs, batch=256, lr=1e-3, log=log)
+    s_ev = torch.from_numpy(ev.sbus).to(dev)
+    v_ev = torch.from_numpy(ev.v0).to(dev)
+    B = ev.batch
+    out = {"train": {"scenarios": int(idx.size), "train_split": n_train, "epochs": epochs,
+                     "params": net.n_params, "data_s": round(prep_s, 2), "train_s": round(rep.seconds, 2),
+                     "val_mse_first": rep.val_loss[0], "val_mse_last": rep.val_loss[-1]},
+           "eval_workload": "10,000 held-out Monte Carlo scenarios of the 1350-bus grid"}
+    ref = None
+    for prec, pname in ((pf.PF_FP64, "fp64"), (pf.PF_FP32_LU, "fp32lu")):
+        wsb = torch.empty(plan.workspace_bytes(B, prec) + 256, dtype=torch.uint8, device=dev)
+        dt_f, rf = timed_solves(lambda: pf.solve_batch(plan, y, s_ev, v_ev, precision=prec, workspace=wsb), steps, warmup)
+        dt_w, rw = timed_solves(lambda: ws.solve_with_warm_start(plan, net, y, s_ev, v_ev, precision=prec, workspace=wsb),
+                                steps, warmup)
+        rw, n_fb = rw
+        if ref is None:
+            ref = rf
+        cf = rf.converged.cpu().numpy().astype(bool)
+        cw = rw.converged.cpu().numpy().astype(bool)
+        both = cw & ref.converged.cpu().numpy().astype(bool)
+        dv = float(np.abs(rw.v.cpu().numpy()[both] - ref.v.cpu().numpy()[both]).max()) if both.any() else None
+        out[pname + "_flat"] = {"flows_per_s": round(int(cf.sum()) / dt_f, 1), "ms": round(dt_f * 1e3, 3),
+                                "iterations_mean": round(float(rf.iters.cpu().numpy()[cf].mean()), 4)}
+        out[pname + "_warm"] = {"flows_per_s": round(int(cw.sum()) / dt_w, 1), "ms": round(dt_w * 1e3, 3),
+                                "iterations_mean": round(float(rw.iters.cpu().numpy()[cw].mean()), 4),
+                                "fallbacks": n_fb, "max_dv_vs_fp64_flat": dv}
+    return out
+
+
+def queue_variant(steps, warmup, log, precision_name="fp32lu"):
+    """The four-grid mix (100/1000/3000/9000 buses with 4000/2000/1000/200 Monte Carlo
+    scenarios): (a) one pf_solve_batch per grid in sequence with the default
+    configuration, (b) every grid's best configuration from the tuner, all grids in one
+    replayed graph of persistent kernels.  Reports aggregate flows/s and, from the queue's
+    per-instance completion ticks, each grid's p50/p99 completion latency."""
+    import torch
+    import gridgen as gg
+    import paper_2101_02270_amd as pf
+    dev = torch.device("cuda", 0)
+    prec = pf.PF_FP32_LU if precision_name == "fp32lu" else pf.PF_FP64
+    grids = []
+    for g, yb, sc in gg.workload("c4"):
+        plan = pf.Plan.from_ybus(yb, g.bus_type)
+        grids.append((g, plan, torch.from_numpy(yb.val).to(dev), torch.from_numpy(sc.sbus).to(dev),
+                      torch.from_numpy(sc.v0).to(dev)))
+    total = sum(int(v.shape[0]) for *_, v in grids)
+
+    def seq():
+        return [pf.solve_batch(plan, y, s, v, precision=prec) for g, plan, y, s, v in grids]
+    dt_seq, r_seq = timed_solves(seq, steps, warmup)
+    t0 = time.perf_counter()
+    tuned = []
+    for g, plan, y, s, v in grids:
+        best, ms = pf.tune(plan, y, s, v, precision=prec, reps=2)
+        tuned.append(best)
+        log(f"[bench] tuned {g.name}: {best} {ms:.3f} ms")
+    tune_s = time.perf_counter() - t0
+    q = pf.Queue()
+    outs = [q.add(plan, y, s, v, **best) for (g, plan, y, s, v), best in zip(grids, tuned)]
+
+    def run_q():
+        q.run()
+        return outs
+    dt_q, _ = timed_solves(run_q, steps, warmup)
+    info = q.info()
+    hz = info["wall_clock_hz"]
+    per_grid = {}
+    n_conv_q = 0
+    for (g, plan, y, s, v), o, best, rs in zip(grids, outs, tuned, r_seq):
+        conv = o.converged.cpu().numpy().astype(bool)
+        n_conv_q += int(conv.sum())
+        lat_ms = o.ticks.cpu().numpy()[conv] / hz * 1e3
+        dv = float((o.v - rs.v).abs().max().item())
+        per_grid[g.name] = {"scenarios": int(v.shape[0]), "config": best,
+                            "iterations_mean": round(float(o.iters.cpu().numpy()[conv].mean()), 4),
+                            "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                            "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                            "max_dv_vs_sequential": dv}
+    n_conv_s = sum(int(r.converged.sum().item()) for r in r_seq)
+    q.close()
+    return {"workload": "4 synthetic grids (100/1000/3000/9000 buses) x 4000/2000/1000/200 Monte Carlo "
+                        "scenarios, flat start, tol 1e-8 pu, max 10 iterations",
+            "precision": precision_name, "instances": total,
+            "sequential_default": {"flows_per_s": round(n_conv_s / dt_seq, 1), "ms": round(dt_seq * 1e3, 3)},
+            "queue_tuned": {"flows_per_s": round(n_conv_q / dt_q, 1), "ms": round(dt_q * 1e3, 3),
+                            "groups": info["n_groups"], "grid": info["grid"], "tune_s": round(tune_s, 2)},
+            "per_grid": per_grid}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +210,12 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--count", type=int, default=0, help="cap the scenario count (testing only)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP32-LU and learned-warm-start variants")
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (scales the HBM "
+                         "byte counters of a profiler run)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -81,6 +224,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        n = 256 * 1024 * 1024 // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_direction": n * 8, "launches": 3}))
+        return
     import gridgen as gg
     import paper_2101_02270_amd as pf
 
@@ -163,6 +315,12 @@ def main():
                      "kernel": "nr_tile_kernel", "kernel_ms": round(kernel_ms, 4),
                      "algorithmic_bytes_per_launch": abytes},
     }
+    if not args.no_variants and args.workload == "c1" and not args.count:
+        log = lambda m: print(m, file=sys.stderr, flush=True)
+        log("[bench] variants: FP32-LU and learned warm start on the held-out set")
+        res["variants"] = warm_start_variants(max(2, args.steps // 2), 1, args.epochs, log)
+        log("[bench] variants: four-grid queue with tuned configurations")
+        res["variants"]["multi_grid"] = queue_variant(max(2, args.steps // 2), 1, log)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(g, yb, sc, tol, max_iter)

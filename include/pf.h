@@ -57,6 +57,7 @@ typedef struct {
     int64_t flops_refactor;         /* multiply-adds of one refactorization                */
     int64_t bytes_iter_fp64;        /* compulsory HBM bytes per instance-iteration, FP64   */
     int64_t bytes_iter_fp32;        /* the same with the LU data in FP32                    */
+    uint64_t pattern_hash;          /* FNV-1a of sizes, bus types, Ybus pattern and order   */
 } pf_plan_info_t;
 
 /* Solver options; pass NULL for the defaults. */
@@ -64,9 +65,14 @@ typedef struct {
     int32_t precision;     /* PF_FP64 (default) or PF_FP32_LU: Jacobian, LU refactor and
                               substitutions in FP32; mismatch, convergence test and
                               voltage update in FP64 (inexact Newton)                      */
-    int32_t tile;          /* instances per workgroup (8, 16 or 32); 0 = automatic          */
-    int32_t waves;         /* wavefronts per workgroup (1..8); 0 = automatic                */
-    int32_t reserved[5];
+    int32_t tile;          /* instances per workgroup: 4, 8 or 16 (FP64), 8, 16 or 32
+                              (FP32-LU); 0 = automatic                                     */
+    int32_t waves;         /* wavefronts per workgroup (2, 4 or 8); 0 = automatic           */
+    int32_t schedule;      /* order in which wavefronts take the panels (single columns and
+                              the angle/|V| column pairs of PQ buses): 0 = by level of the
+                              column DAG (default), 1 = elimination order; both are
+                              topological, results differ only by rounding order          */
+    int32_t reserved[4];
 } pf_solve_opts;
 
 /*
@@ -147,6 +153,101 @@ int pf_eval_factor(pf_plan plan, int32_t batch, const double *ybus, const double
 int pf_eval_step(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
                  const double *v, const pf_solve_opts *opts, void *workspace,
                  size_t workspace_bytes, double *dx_out, void *stream);
+
+/*
+ * Learned warm start (an addition to the paper's method: a small network maps the
+ * specified injections to initial voltages; Newton still iterates to the same tolerance,
+ * so the network only changes the iteration count).  BF16 operands, FP32 accumulation;
+ * all matrices row-major [device].
+ *
+ * pf_mlp_gemm: C[M][N] = op(A) op(B) with op(A) = A ([M][K]) or A^T (A stored [K][M]) when
+ *   trans_a, op(B) = B ([K][N]) or B^T (B stored [N][K]) when trans_b; epilogue
+ *   z = C + bias[n] (bias may be NULL) written to z_out (FP32, may be NULL), and
+ *   act = GELU(z) (exact erf form) when gelu else z, written as BF16 and/or FP32 (either
+ *   may be NULL).  Runs on the matrix cores.
+ * pf_mlp_act_backward: dz = d_act * GELU'(z) (or d_act when !gelu), rounded to BF16, and
+ *   db[n] = sum over rows of dz (FP32, may be NULL); [M][N].
+ * pf_mlp_mse: grad = 2 (pred - target) / count; loss_parts[n_parts] partial sums of
+ *   (pred - target)^2 / count (their sum is the loss).
+ * pf_mlp_adam: one Adam step (bias-corrected, step >= 1) on FP32 master weights w with
+ *   moments m, v; the BF16 copy w_bf16 (may be NULL) is refreshed.
+ * pf_mlp_to_bf16: y = x rounded to nearest-even BF16.
+ * pf_mlp_features: x_bf16 [batch][2 nf_bus] = z-scored (P, Q) of PQ buses and (P, |V| set-
+ *   point) of PV buses listed in feat_bus (sbus, v0 as in pf_solve_batch; mu, sigma
+ *   [2 nf_bus]).
+ * pf_mlp_warm_v0: v0 [batch][n_bus][2] from the network output out [batch][2 nf_bus]
+ *   ((|V|, angle) per feature bus, de-normalised with mu, sigma); PV |V| and the REF bus
+ *   keep the set-points of v_set ([batch][n_bus][2]); non-finite outputs fall back to v_set.
+ */
+int pf_mlp_gemm(int32_t M, int32_t N, int32_t K, int32_t trans_a, int32_t trans_b, const uint16_t *a,
+                const uint16_t *b, const float *bias, int32_t gelu, float *z_out, uint16_t *act_bf16_out,
+                float *act_f32_out, void *stream);
+int pf_mlp_act_backward(int32_t M, int32_t N, const float *d_act, const float *z, int32_t gelu,
+                        uint16_t *dz_bf16, float *db, void *stream);
+int pf_mlp_mse(int64_t count, const float *pred, const float *target, float *grad, float *loss_parts,
+               int32_t n_parts, void *stream);
+int pf_mlp_adam(int64_t n, float *w, uint16_t *w_bf16, const float *grad, float *m, float *v, float lr,
+                float beta1, float beta2, float eps, int32_t step, void *stream);
+int pf_mlp_to_bf16(int64_t n, const float *x, uint16_t *y, void *stream);
+int pf_mlp_features(int32_t batch, int32_t n_bus, const double *sbus, const double *v0,
+                    const int8_t *bus_type, const int32_t *feat_bus, int32_t nf_bus, const float *mu,
+                    const float *sigma, uint16_t *x_bf16, void *stream);
+int pf_mlp_warm_v0(int32_t batch, int32_t n_bus, const float *out, const int32_t *feat_bus,
+                   int32_t nf_bus, const float *mu, const float *sigma, const int8_t *bus_type,
+                   const double *v_set, double *v0, void *stream);
+
+/*
+ * Multi-pattern queue (an addition to the paper's method, which solves one grid per
+ * launch): instances of several grids, each with its own plan and configuration, run in
+ * one replayable graph.  Items that share precision and waves form one persistent kernel
+ * whose workgroups take tiles from a device counter, largest cost per tile first.
+ *
+ * pf_queue_create: an empty queue bound to the current device.
+ * pf_queue_add: appends one item; arguments as in pf_solve_batch (opts selects precision,
+ *   tile, waves and schedule, e.g. from pf_tune).  done_ticks_out [device, may be NULL]
+ *   receives, per instance, the device wall-clock ticks from the start of the run to the
+ *   moment the instance's results were written (pf_queue_info gives the tick rate).  All
+ *   pointers are borrowed: they must stay valid, and keep their addresses, for every
+ *   later pf_queue_run.  An item with batch 0 is accepted and ignored.  Adding to a queue
+ *   that has run makes the next run rebuild it.
+ * pf_queue_run: enqueues the whole queue on stream (NULL = default stream).  The first run
+ *   after an addition allocates the queue's workspace (device memory owned by the queue),
+ *   uploads the items and builds the graph; later runs only replay it.  Runs of one queue
+ *   share its workspace and counters and must not overlap.
+ * pf_queue_destroy: waits for the device, then frees the graph and workspace.
+ */
+typedef struct pf_queue_s *pf_queue;
+typedef struct {
+    int32_t n_items, n_groups;     /* items added; persistent kernels of the built graph    */
+    int32_t built;                 /* 1 when the graph is current                           */
+    int32_t grid[6];               /* workgroups of each persistent kernel                  */
+    int64_t n_tiles, n_instances;  /* over all items                                       */
+    size_t workspace_bytes;        /* device memory held by the queue                      */
+    double wall_clock_hz;          /* rate of the done_ticks clock                          */
+} pf_queue_info_t;
+
+int pf_queue_create(pf_queue *out);
+int pf_queue_add(pf_queue queue, pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
+                 const double *v0, double tol, int32_t max_iter, const pf_solve_opts *opts, double *v_out,
+                 int32_t *iters_out, uint8_t *converged_out, int8_t *status_out, uint64_t *done_ticks_out);
+int pf_queue_run(pf_queue queue, void *stream);
+int pf_queue_info(pf_queue queue, pf_queue_info_t *out);
+void pf_queue_destroy(pf_queue queue);
+
+/*
+ * pf_tune: times every configuration (tile, waves, schedule) that fits in LDS on the given
+ * instances (the same arguments as pf_solve_batch) with reps timed solves after one
+ * untimed one, and returns the fastest in best_out (its mean ms per solve in
+ * best_ms_out, may be NULL).  waves = 0 tries every workgroup size, otherwise only that
+ * one (so that tuned items of a queue share one persistent kernel).  Results are cached in
+ * the process, keyed by the plan's pattern hash, device, precision, waves and batch;
+ * flags & PF_TUNE_FORCE re-times a cached key.  Allocates and frees its own device
+ * buffers; synchronises with stream.
+ */
+enum { PF_TUNE_FORCE = 1 };
+int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus, const double *v0, double tol,
+            int32_t max_iter, int32_t precision, int32_t waves, int32_t reps, int32_t flags,
+            pf_solve_opts *best_out, double *best_ms_out, void *stream);
 
 /* Release the plan and its device memory. */
 void pf_plan_destroy(pf_plan plan);

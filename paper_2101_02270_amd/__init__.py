@@ -24,7 +24,10 @@ PF_ST_CONVERGED, PF_ST_MAXITER, PF_ST_NONFINITE, PF_ST_PIVOT, PF_ST_INTERNAL = 0
 
 EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
             "pf_workspace_bytes", "pf_solve_batch", "pf_eval_mismatch", "pf_eval_factor",
-            "pf_eval_step", "pf_plan_destroy", "pf_last_error"]
+            "pf_eval_step", "pf_plan_destroy", "pf_last_error", "pf_mlp_gemm",
+            "pf_mlp_act_backward", "pf_mlp_mse", "pf_mlp_adam", "pf_mlp_to_bf16",
+            "pf_mlp_features", "pf_mlp_warm_v0", "pf_queue_create", "pf_queue_add",
+            "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune"]
 
 
 class PfError(RuntimeError):
@@ -37,12 +40,20 @@ class _PlanInfo(ctypes.Structure):
                 ("nnz_lu", ctypes.c_int32), ("n_levels", ctypes.c_int32),
                 ("n_bs_levels", ctypes.c_int32), ("max_col", ctypes.c_int32),
                 ("n_updates", ctypes.c_int64), ("flops_refactor", ctypes.c_int64),
-                ("bytes_iter_fp64", ctypes.c_int64), ("bytes_iter_fp32", ctypes.c_int64)]
+                ("bytes_iter_fp64", ctypes.c_int64), ("bytes_iter_fp32", ctypes.c_int64),
+                ("pattern_hash", ctypes.c_uint64)]
 
 
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tile", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class _QueueInfo(ctypes.Structure):
+    _fields_ = [("n_items", ctypes.c_int32), ("n_groups", ctypes.c_int32), ("built", ctypes.c_int32),
+                ("grid", ctypes.c_int32 * 6), ("n_tiles", ctypes.c_int64),
+                ("n_instances", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
+                ("wall_clock_hz", ctypes.c_double)]
 
 
 _lib = None
@@ -76,6 +87,23 @@ def lib():
             getattr(L, f).argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.POINTER(_Opts), _vp,
                                       ctypes.c_size_t, _vp, _vp]
         L.pf_plan_destroy.argtypes = [_vp]
+        i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+        L.pf_mlp_gemm.argtypes = [i32, i32, i32, i32, i32, _vp, _vp, _vp, i32, _vp, _vp, _vp, _vp]
+        L.pf_mlp_act_backward.argtypes = [i32, i32, _vp, _vp, i32, _vp, _vp, _vp]
+        L.pf_mlp_mse.argtypes = [i64, _vp, _vp, _vp, _vp, i32, _vp]
+        L.pf_mlp_adam.argtypes = [i64, _vp, _vp, _vp, _vp, _vp, f32, f32, f32, f32, i32, _vp]
+        L.pf_mlp_to_bf16.argtypes = [i64, _vp, _vp, _vp]
+        L.pf_mlp_features.argtypes = [i32, i32, _vp, _vp, _vp, _vp, i32, _vp, _vp, _vp, _vp]
+        L.pf_mlp_warm_v0.argtypes = [i32, i32, _vp, _vp, i32, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.pf_queue_create.argtypes = [ctypes.POINTER(_vp)]
+        L.pf_queue_add.argtypes = [_vp, _vp, i32, _vp, _vp, _vp, ctypes.c_double, i32,
+                                   ctypes.POINTER(_Opts), _vp, _vp, _vp, _vp, _vp]
+        L.pf_queue_run.argtypes = [_vp, _vp]
+        L.pf_queue_info.argtypes = [_vp, ctypes.POINTER(_QueueInfo)]
+        L.pf_queue_destroy.argtypes = [_vp]
+        L.pf_queue_destroy.restype = None
+        L.pf_tune.argtypes = [_vp, i32, _vp, _vp, _vp, ctypes.c_double, i32, i32, i32, i32, i32,
+                              ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_double), _vp]
         L.pf_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -210,7 +238,7 @@ def _as_pairs(x, name):
 
 def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
                 precision: int = PF_FP64, tile: int = 0, waves: int = 0, workspace=None,
-                stream=None, out: Optional[Result] = None) -> Result:
+                stream=None, out: Optional[Result] = None, schedule: int = 0) -> Result:
     """Run pf_solve_batch on device tensors: ybus complex128 [nnz_y], sbus complex128 [B][n],
     v0 float64 [B][n][2].  Returns device tensors (valid once the stream synchronises)."""
     torch = _torch()
@@ -224,7 +252,7 @@ def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 1
                      iters=torch.empty(B, dtype=torch.int32, device=v0.device),
                      converged=torch.empty(B, dtype=torch.uint8, device=v0.device),
                      status=torch.empty(B, dtype=torch.int8, device=v0.device))
-    opts = _Opts(precision, tile, waves)
+    opts = _Opts(precision, tile, waves, schedule)
     workspace, wp, avail = _workspace(plan, B, opts, workspace)
     rc = lib().pf_solve_batch(plan._h, B, yp, 0, sp, vp, float(tol), int(max_iter), ctypes.byref(opts),
                               wp, avail, _vp(out.v.data_ptr()), _vp(out.iters.data_ptr()),
@@ -275,3 +303,83 @@ def eval_step(plan: Plan, ybus, sbus, v, precision=PF_FP64, tile=0, waves=0, **k
     """Newton step dx [B][N] (unknown order) solving J(V) dx = F(V)."""
     B = int(v.shape[0])
     return _eval(lib().pf_eval_step, plan, ybus, sbus, v, (B, plan.N), precision, tile, waves, **kw)
+
+
+def tune(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
+         precision: int = PF_FP64, waves: int = 0, reps: int = 2, force: bool = False,
+         stream=None):
+    """pf_tune on device tensors shaped as for solve_batch.  Returns
+    ({"precision", "tile", "waves", "schedule"}, mean ms per solve)."""
+    torch = _torch()
+    B = int(v0.shape[0])
+    yp, _ = _ybus_view(plan, ybus)
+    sp = _dev_ptr(_as_pairs(sbus, "sbus"), torch.float64, (B, plan.n, 2), "sbus")
+    vp = _dev_ptr(v0, torch.float64, (B, plan.n, 2), "v0")
+    best = _Opts()
+    ms = ctypes.c_double(0.0)
+    rc = lib().pf_tune(plan._h, B, yp, sp, vp, float(tol), int(max_iter), int(precision), int(waves),
+                       int(reps), 1 if force else 0, ctypes.byref(best), ctypes.byref(ms),
+                       _stream_ptr(stream))
+    _check(rc, "pf_tune")
+    return ({"precision": best.precision, "tile": best.tile, "waves": best.waves,
+             "schedule": best.schedule}, ms.value)
+
+
+class Queue:
+    """pf_queue_*: several plans' batches solved by one replayable graph of persistent
+    kernels.  Every tensor handed to add() is kept referenced here, because the graph
+    holds its address."""
+
+    def __init__(self):
+        h = _vp()
+        _check(lib().pf_queue_create(ctypes.byref(h)), "pf_queue_create")
+        self._h = h
+        self._keep = []
+        self.results = []
+
+    def add(self, plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
+            precision: int = PF_FP64, tile: int = 0, waves: int = 0, schedule: int = 0,
+            ticks: bool = True) -> Result:
+        torch = _torch()
+        B = int(v0.shape[0])
+        yp, yv = _ybus_view(plan, ybus)
+        s2 = _as_pairs(sbus, "sbus")
+        sp = _dev_ptr(s2, torch.float64, (B, plan.n, 2), "sbus")
+        vp = _dev_ptr(v0, torch.float64, (B, plan.n, 2), "v0")
+        dev = v0.device
+        out = Result(v=torch.empty((B, plan.n, 2), dtype=torch.float64, device=dev),
+                     iters=torch.empty(B, dtype=torch.int32, device=dev),
+                     converged=torch.empty(B, dtype=torch.uint8, device=dev),
+                     status=torch.empty(B, dtype=torch.int8, device=dev))
+        out.ticks = torch.zeros(B, dtype=torch.int64, device=dev) if ticks else None
+        opts = _Opts(precision, tile, waves, schedule)
+        rc = lib().pf_queue_add(self._h, plan._h, B, yp, sp, vp, float(tol), int(max_iter),
+                                ctypes.byref(opts), _vp(out.v.data_ptr()), _vp(out.iters.data_ptr()),
+                                _vp(out.converged.data_ptr()), _vp(out.status.data_ptr()),
+                                _vp(out.ticks.data_ptr()) if ticks else None)
+        _check(rc, "pf_queue_add")
+        self._keep.append((plan, yv, s2, v0, out))
+        self.results.append(out)
+        return out
+
+    def run(self, stream=None):
+        _check(lib().pf_queue_run(self._h, _stream_ptr(stream)), "pf_queue_run")
+
+    def info(self) -> dict:
+        q = _QueueInfo()
+        _check(lib().pf_queue_info(self._h, ctypes.byref(q)), "pf_queue_info")
+        d = {f: getattr(q, f) for f, _ in _QueueInfo._fields_}
+        d["grid"] = list(q.grid)[: q.n_groups]
+        return d
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pf_queue_destroy(self._h)
+        self._h = None
+        self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

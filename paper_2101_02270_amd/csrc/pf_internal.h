@@ -50,6 +50,9 @@ struct HostPlan {
     // panels: a PQ bus's angle and |V| columns (adjacent, same row list) form a 2-column
     // supernode; every other column is a panel of its own
     std::vector<int32_t> panel_ptr;               // first column of each panel, then N
+    // processing orders of the panels: by refactorization level (a topological order of
+    // the column DAG) and by back-substitution level (topological for the row DAG)
+    std::vector<int32_t> lu_seq, bs_seq;
     // right-hand side and update maps
     std::vector<int32_t> bus_peq, bus_qeq;        // bus -> position of its P / Q equation, -1
     std::vector<int32_t> pos_upd;                 // position j -> bus * 2 + (unknown is |V|)
@@ -69,7 +72,7 @@ struct DevPlan {
     const int32_t *lev_ptr, *lev_cols, *bs_lev_ptr, *bs_lev_rows;
     const int32_t *bs_ptr, *bs_pos, *bs_col;
     const int32_t *bus_peq, *bus_qeq, *pos_upd;
-    const int32_t *panel_ptr;
+    const int32_t *panel_ptr, *lu_seq, *bs_seq;
     int n_panels;
 };
 

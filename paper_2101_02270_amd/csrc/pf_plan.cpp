@@ -327,6 +327,22 @@ int analyze(int n, int nnzy, const int32_t *row_ptr, const int32_t *col_idx,
         j += pair ? 2 : 1;
     }
     h.panel_ptr.push_back(N);
+    {
+        const int np = (int)h.panel_ptr.size() - 1;
+        std::vector<int> lk(np), bk(np);
+        for (int q = 0; q < np; q++) {
+            lk[q] = h.level[h.panel_ptr[q]];
+            bk[q] = blev[h.panel_ptr[q + 1] - 1];
+        }
+        h.lu_seq.resize(np);
+        h.bs_seq.resize(np);
+        std::iota(h.lu_seq.begin(), h.lu_seq.end(), 0);
+        std::iota(h.bs_seq.begin(), h.bs_seq.end(), 0);
+        std::stable_sort(h.lu_seq.begin(), h.lu_seq.end(), [&](int a, int b) { return lk[a] < lk[b]; });
+        std::stable_sort(h.bs_seq.begin(), h.bs_seq.end(), [&](int a, int b) {
+            return bk[a] != bk[b] ? bk[a] < bk[b] : a > b;
+        });
+    }
 
     // ---- right-hand side and update maps
     h.bus_peq.assign(n, -1);

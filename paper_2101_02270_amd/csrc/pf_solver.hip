@@ -29,9 +29,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "pf_internal.h"
 
@@ -41,6 +45,9 @@ static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 
 enum Mode { MODE_SOLVE = 0, MODE_MISMATCH = 1, MODE_FACTOR = 2, MODE_STEP = 3 };
+
+constexpr int BUILD_CHUNK = 2;   // Jacobian entries per lane whose loads are issued together
+constexpr int UPD_GROUP = 4;     // column updates whose operand loads are issued together
 
 struct KArgs {
     DevPlan p;
@@ -58,6 +65,10 @@ struct KArgs {
     int8_t *status_out;
     double *aux_out;            // F, LU or dx for the single-step modes
     double *aux2_out;           // max |F| for MODE_MISMATCH
+    unsigned long long *done_ticks;        // per-instance completion tick (may be null)
+    const unsigned long long *t0;          // start tick the completion ticks are relative to
+    int sched;                  // 0: level order, 1: elimination order
+    int tsz;                    // instances per tile (the body's T), read by the queue kernel
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -73,7 +84,7 @@ __device__ __forceinline__ void wave_sync()
 //                 dS_i/d|V_i|   = S_i / |V_i| + |V_i| conj Y_ii
 // P equations take the real part, Q equations the imaginary part.
 // The column's own bus k supplies V_k, |V_k| and I_k (loaded once per panel); each
-// off-diagonal entry loads only V_i and Y_ik.  The angle and |V| columns of a PQ bus share
+// off-diagonal entry needs only V_i and Y_ik (loaded by the caller).  The angle and |V| columns of a PQ bus share
 // the entry's Ybus element and row, so one call yields both derivatives:
 //   angle:  off-diagonal -j w, diagonal j (S_k - |V_k|^2 conj Y_kk)
 //   |V|:    off-diagonal w / |V_k|, diagonal S_k / |V_k| + |V_k| conj Y_kk
@@ -82,14 +93,12 @@ struct JacPair {
     double th, vm;
 };
 
-__device__ __forceinline__ JacPair jac_entry(const JacDesc d, const double *ybus, const double2 *Vc_t,
-                                             double2 vk, double vmk, double2 ik)
+__device__ __forceinline__ JacPair jac_entry(const JacDesc d, double2 y, double2 v, double2 vk, double vmk,
+                                             double2 ik)
 {
     if (d.p < 0) return JacPair{0.0, 0.0};
-    const double2 y = reinterpret_cast<const double2 *>(ybus)[d.p];
     double tr, ti, vr, vi;     // d/d angle and d/d|V| of S_i, complex
     if (d.i != d.k) {
-        const double2 v = Vc_t[0];
         const double cr = y.x * vk.x - y.y * vk.y, ci = y.x * vk.y + y.y * vk.x;     // Y_ik V_k
         const double wr = v.x * cr + v.y * ci, wi = v.y * cr - v.x * ci;              // V_i conj(.)
         tr = wi; ti = -wr;
@@ -130,8 +139,34 @@ __device__ __forceinline__ void wait_published(unsigned char *flags, int j, int 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Wait until every row bs_col[q], q0 <= q < q1, is published: the lanes poll their share of
+// the flags in parallel and the wavefront votes.  Bounded like wait_published.
+__device__ __forceinline__ void wait_all_published(unsigned char *flags, const int32_t *cols, int q0, int q1,
+                                                   int lane, int *err)
+{
+    for (int qb = q0; qb < q1; qb += 64) {
+        const int q = qb + lane;
+        const int c = q < q1 ? cols[q] : -1;
+        for (unsigned spins = 0;; ++spins) {
+            const bool ok = c < 0 || __hip_atomic_load(&flags[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (__all(ok)) break;
+            const int e = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            if (e) break;
+            if (spins >= (1u << 22)) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// The whole Newton loop of one tile (T instances) by one workgroup.  Called by the
+// one-tile-per-workgroup kernel and by the persistent multi-pattern queue kernel.
 template <typename R, int T, int NW>
-__global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
+__device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
 {
     constexpr int SL = 64 / T;          // sub-lanes per instance inside a wavefront
     constexpr int NT = NW * 64;
@@ -146,12 +181,13 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
 
     const DevPlan &P = a.p;
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    // wavefront index as a scalar: every plan lookup keyed by it becomes a scalar load and
+    // every loop over panels a scalar loop
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int t = lane % T;
     const int s = lane / T;
     const int slot = tid / T;
-    const int tile = blockIdx.x;
     const int b = tile * T + t;
     const bool valid = b < a.batch;
     const int n = P.n;
@@ -271,9 +307,11 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
             __hip_atomic_store(&done[w], (unsigned char)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __syncthreads();
         // Panels (one column, or the angle/|V| pair of a PQ bus sharing one row list) in
-        // elimination order, round-robin over the wavefronts: the smallest unfinished panel
-        // always has every source published, so some wavefront always makes progress.
-        for (int pi = wave; pi < P.n_panels; pi += NW) {
+        // level order, round-robin over the wavefronts.  The order is topological, so the
+        // earliest unfinished panel always has every source published and some wavefront
+        // always makes progress; level order keeps independent panels side by side.
+        for (int q = wave; q < P.n_panels; q += NW) {
+            const int pi = a.sched ? q : P.lu_seq[q];
             const int j = P.panel_ptr[pi];
             const bool two = P.panel_ptr[pi + 1] - j == 2;
             const int cs = P.col_ptr[j];
@@ -283,36 +321,98 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
                 const int kb = P.pos_upd[j] >> 1;      // bus of the panel's unknowns
                 const double2 vk = Vc[kb * T + t], ik = Ic[kb * T + t];
                 const double vmk = Vm[kb * T + t];
-                for (int e = s; e < cnt; e += SL) {
-                    const JacDesc d0 = P.desc[cs + e];
-                    const JacPair jp = jac_entry(d0, a.ybus, Vc + d0.i * T + t, vk, vmk, ik);
-                    xw[e * T + t] = (R)((d0.kind & 1) ? jp.vm : jp.th);
-                    if (two) xw1[e * T + t] = (R)jp.vm;
+                // descriptors of this lane's entries first, then every operand load, so that
+                // the loads of several entries are in flight together
+                for (int e0 = s; e0 < cnt; e0 += BUILD_CHUNK * SL) {
+                    JacDesc dd[BUILD_CHUNK];
+#pragma unroll
+                    for (int q = 0; q < BUILD_CHUNK; q++) {
+                        const int e = e0 + q * SL;
+                        dd[q] = e < cnt ? P.desc[cs + e] : JacDesc{-1, 0, 0, 0};
+                    }
+                    double2 yy[BUILD_CHUNK], vv[BUILD_CHUNK];
+#pragma unroll
+                    for (int q = 0; q < BUILD_CHUNK; q++) {
+                        yy[q] = dd[q].p >= 0 ? reinterpret_cast<const double2 *>(a.ybus)[dd[q].p] : make_double2(0.0, 0.0);
+                        vv[q] = (dd[q].p >= 0 && dd[q].i != dd[q].k) ? Vc[dd[q].i * T + t] : vk;
+                    }
+#pragma unroll
+                    for (int q = 0; q < BUILD_CHUNK; q++) {
+                        const int e = e0 + q * SL;
+                        if (e < cnt) {
+                            const JacPair jp = jac_entry(dd[q], yy[q], vv[q], vk, vmk, ik);
+                            xw[e * T + t] = (R)((dd[q].kind & 1) ? jp.vm : jp.th);
+                            if (two) xw1[e * T + t] = (R)jp.vm;
+                        }
+                    }
                 }
             }
             if (s == 0) {
                 ysl[t] = Yv[j * T + t];
                 if (two) ysl1[t] = Yv[(j + 1) * T + t];
             }
+            // Updates in ascending source order.  After waiting for the first pending source,
+            // the run of following updates whose sources are already published (up to
+            // UPD_GROUP) has its operand loads issued together, then the updates are applied
+            // one after another in LDS (the order of the arithmetic is unchanged).
             const int u0 = P.upd_ptr[j], u1 = P.upd_ptr[j + 1];
-            Update upn{};
-            if (u0 < u1) upn = P.upd[u0];
-            for (int u = u0; u < u1; u++) {
-                const Update up = upn;
-                if (u + 1 < u1) upn = P.upd[u + 1];     // next descriptor in flight meanwhile
-                const int krel = up.krel_lcnt & 0xffff, lcnt = up.krel_lcnt >> 16;
-                wait_published(done, up.k, err);
-                wave_sync();
-                const R m0 = xw[krel * T + t];
-                const R m1 = two ? xw1[krel * T + t] : (R)0;
-                for (int r = s; r < lcnt; r += SL) {
-                    const R l = LU[(size_t)(up.lbeg + r) * T + t];
-                    const int tr = P.rel[up.roff + r];
-                    xw[tr * T + t] = fma(-m0, l, xw[tr * T + t]);
-                    if (two) xw1[tr * T + t] = fma(-m1, l, xw1[tr * T + t]);
-                    if (tr == dr) ysl[t] = fma(-l, Yv[up.k * T + t], ysl[t]);
-                    else if (two && tr == dr + 1) ysl1[t] = fma(-l, Yv[up.k * T + t], ysl1[t]);
+            for (int ub = u0; ub < u1;) {
+                Update ups[UPD_GROUP];
+                ups[0] = P.upd[ub];
+                wait_published(done, ups[0].k, err);
+                int gcnt = 1;
+#pragma unroll
+                for (int g = 1; g < UPD_GROUP; g++) {
+                    if (gcnt == g && ub + g < u1) {
+                        ups[g] = P.upd[ub + g];
+                        const int f = __builtin_amdgcn_readfirstlane((int)__hip_atomic_load(
+                            &done[ups[g].k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                        if (f) gcnt = g + 1;
+                    }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                R lv[UPD_GROUP], yk[UPD_GROUP];
+                int rv[UPD_GROUP];
+#pragma unroll
+                for (int g = 0; g < UPD_GROUP; g++) {
+                    lv[g] = 0; yk[g] = 0; rv[g] = -1;
+                    if (g < gcnt) {
+                        const int lcnt = ups[g].krel_lcnt >> 16;
+                        if (s < lcnt) {
+                            lv[g] = LU[(size_t)(ups[g].lbeg + s) * T + t];
+                            rv[g] = P.rel[ups[g].roff + s];
+                        }
+                        yk[g] = Yv[ups[g].k * T + t];
+                    }
+                }
+                wave_sync();
+#pragma unroll
+                for (int g = 0; g < UPD_GROUP; g++) {
+                    if (g < gcnt) {
+                        const Update up = ups[g];
+                        const int krel = up.krel_lcnt & 0xffff, lcnt = up.krel_lcnt >> 16;
+                        const R m0 = xw[krel * T + t];
+                        const R m1 = two ? xw1[krel * T + t] : (R)0;
+                        if (rv[g] >= 0) {
+                            const int tr = rv[g];
+                            const R l = lv[g];
+                            xw[tr * T + t] = fma(-m0, l, xw[tr * T + t]);
+                            if (two) xw1[tr * T + t] = fma(-m1, l, xw1[tr * T + t]);
+                            if (tr == dr) ysl[t] = fma(-l, yk[g], ysl[t]);
+                            else if (two && tr == dr + 1) ysl1[t] = fma(-l, yk[g], ysl1[t]);
+                        }
+                        for (int r = s + SL; r < lcnt; r += SL) {
+                            const R l = LU[(size_t)(up.lbeg + r) * T + t];
+                            const int tr = P.rel[up.roff + r];
+                            xw[tr * T + t] = fma(-m0, l, xw[tr * T + t]);
+                            if (two) xw1[tr * T + t] = fma(-m1, l, xw1[tr * T + t]);
+                            if (tr == dr) ysl[t] = fma(-l, yk[g], ysl[t]);
+                            else if (two && tr == dr + 1) ysl1[t] = fma(-l, yk[g], ysl1[t]);
+                        }
+                        wave_sync();
+                    }
+                }
+                ub += gcnt;
             }
             wave_sync();
             const R d = xw[dr * T + t];
@@ -358,16 +458,17 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
         __syncthreads();
 
         // ============================ BS: backward substitution and voltage update
-        // Panels in reverse elimination order.  For a pair (j, j+1) the rows share their
+        // Panels in back-substitution level order.  For a pair (j, j+1) the rows share their
         // column set i > j+1, and U(j, i), U(j+1, i) sit next to each other in column i.
         const bool upd_v = (a.mode == MODE_SOLVE);
-        for (int pi = P.n_panels - 1 - wave; pi >= 0; pi -= NW) {
+        for (int q = wave; q < P.n_panels; q += NW) {
+            const int pi = a.sched ? P.n_panels - 1 - q : P.bs_seq[q];
             const int j = P.panel_ptr[pi];
             const bool two = P.panel_ptr[pi + 1] - j == 2;
             const int jl = two ? j + 1 : j;            // the panel's last row
             R acc0 = 0, acc1 = 0;
             const int q0 = P.bs_ptr[jl], q1 = P.bs_ptr[jl + 1];
-            for (int q = q0; q < q1; q++) wait_published(done, P.bs_col[q], err);
+            wait_all_published(done, P.bs_col, q0, q1, lane, err);
             for (int q = q0 + s; q < q1; q += SL) {
                 const R z = Yv[P.bs_col[q] * T + t];
                 const size_t pq = (size_t)P.bs_pos[q];
@@ -423,6 +524,7 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
             a.v_out[o + 1] = Va[i * T + t];
         }
         if (s == 0 && wave == 0) {
+            if (a.done_ticks) a.done_ticks[b] = wall_clock64() - *a.t0;
             const int st = s_err ? PF_ST_INTERNAL : s_status[t];
             a.iters_out[b] = s_iters[t];
             a.conv_out[b] = st == PF_ST_CONVERGED ? 1 : 0;
@@ -431,9 +533,58 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
     }
 }
 
+template <typename R, int T, int NW>
+__global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
+{
+    nr_tile_body<R, T, NW>(a, blockIdx.x);
+}
+
+// Persistent launch over a queue of work items (one per pattern / batch): workgroups pop
+// tiles from a global counter until every item's tiles are done.  prefix[i] is the first
+// tile of item i (prefix[nitems] = total); items are ordered by the caller.
+// Items may use different tile sizes: the body is selected per item (the workgroup size,
+// set by NW, is common to the launch).  Every wave leaves the loop once the counter has
+// passed the last tile, so the grid always drains.
+template <typename R, int NW>
+__global__ __launch_bounds__(NW * 64) void nr_queue_kernel(const KArgs *items, const int *prefix, int nitems,
+                                                           int *counter)
+{
+    __shared__ int s_tile;
+    const int total = prefix[nitems];
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+        __syncthreads();
+        const int tg = __builtin_amdgcn_readfirstlane(s_tile);
+        if (tg >= total) break;
+        int it = 0;
+        while (it + 1 < nitems && prefix[it + 1] <= tg) it++;
+        const KArgs &a = items[it];
+        const int tile = tg - prefix[it];
+        const int tsz = __builtin_amdgcn_readfirstlane(a.tsz);
+        if constexpr (sizeof(R) == 8) {
+            if (tsz == 4) nr_tile_body<R, 4, NW>(a, tile);
+            else if (tsz == 8) nr_tile_body<R, 8, NW>(a, tile);
+            else nr_tile_body<R, 16, NW>(a, tile);
+        } else {
+            if (tsz == 8) nr_tile_body<R, 8, NW>(a, tile);
+            else if (tsz == 16) nr_tile_body<R, 16, NW>(a, tile);
+            else nr_tile_body<R, 32, NW>(a, tile);
+        }
+    }
+}
+
+// Resets the queue's tile counters and records the launch's start tick; a kernel rather than
+// a memset so that it can sit inside a graph.
+__global__ void queue_reset_kernel(int *counters, int n, unsigned long long *t0)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) counters[i] = 0;
+    if (threadIdx.x == 0) *t0 = wall_clock64();
+}
+
 // ------------------------------------------------------------------ launch configuration
 struct Config {
-    int precision, tile, waves;
+    int precision, tile, waves, schedule;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -466,15 +617,15 @@ static constexpr size_t kLdsLimit = 160 * 1024 - 8192;
 static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c, std::string &err)
 {
     c.precision = o ? o->precision : PF_FP64;
+    c.schedule = o ? o->schedule : 0;
+    if (c.schedule != 0 && c.schedule != 1) { err = "schedule must be 0 or 1"; return false; }
     const int tile = o ? o->tile : 0, waves = o ? o->waves : 0;
     if (c.precision != PF_FP64 && c.precision != PF_FP32_LU) { err = "unknown precision"; return false; }
     const bool fp64 = c.precision == PF_FP64;
     if (tile != 0 && !(fp64 ? (tile == 4 || tile == 8 || tile == 16) : (tile == 8 || tile == 16 || tile == 32))) {
         err = "unsupported tile size for this precision"; return false;
     }
-    if (waves != 0 && waves != 2 && waves != 4 && waves != 8 && waves != 16) {
-        err = "waves must be 2, 4, 8 or 16"; return false;
-    }
+    if (waves != 0 && waves != 2 && waves != 4 && waves != 8) { err = "waves must be 2, 4 or 8"; return false; }
     static const int cand64[][2] = {{8, 4}, {4, 8}, {8, 2}, {4, 4}, {4, 2}};
     static const int cand32[][2] = {{16, 4}, {8, 8}, {16, 2}, {8, 4}, {8, 2}};
     for (const auto &cw : (fp64 ? cand64 : cand32)) {
@@ -487,19 +638,20 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
     return false;
 }
 
+template <typename F>
+static hipError_t allow_lds(F fn, size_t lds)
+{
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(160 * 1024 - 8192));
+}
+
 template <typename R, int T, int NW>
 static hipError_t launch_t(const KArgs &a, int grid, size_t lds, hipStream_t st)
 {
     auto fn = nr_tile_kernel<R, T, NW>;
-    if (lds > 64 * 1024) {
-        static std::once_flag once;
-        static hipError_t attr_err = hipSuccess;
-        std::call_once(once, [&] {
-            attr_err = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
-        });
-        if (attr_err != hipSuccess) return attr_err;
-    }
+    const hipError_t e = allow_lds(fn, lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(NW * 64), lds, st, a);
     return hipGetLastError();
 }
@@ -508,9 +660,21 @@ static hipError_t launch_t(const KArgs &a, int grid, size_t lds, hipStream_t st)
     switch (c.waves) {                                                         \
     case 2: return launch_t<R, T, 2>(a, grid, lds, st);                        \
     case 4: return launch_t<R, T, 4>(a, grid, lds, st);                        \
-    case 8: return launch_t<R, T, 8>(a, grid, lds, st);                        \
-    default: return launch_t<R, T, 16>(a, grid, lds, st);                      \
+    default: return launch_t<R, T, 8>(a, grid, lds, st);                       \
     }
+
+// The persistent queue kernel for a precision and a workgroup size.
+static const void *queue_kernel(int precision, int waves)
+{
+    if (precision == PF_FP64) {
+        if (waves == 2) return reinterpret_cast<const void *>(nr_queue_kernel<double, 2>);
+        if (waves == 4) return reinterpret_cast<const void *>(nr_queue_kernel<double, 4>);
+        return reinterpret_cast<const void *>(nr_queue_kernel<double, 8>);
+    }
+    if (waves == 2) return reinterpret_cast<const void *>(nr_queue_kernel<float, 2>);
+    if (waves == 4) return reinterpret_cast<const void *>(nr_queue_kernel<float, 4>);
+    return reinterpret_cast<const void *>(nr_queue_kernel<float, 8>);
+}
 
 static hipError_t launch(const Config &c, const KArgs &a, int grid, size_t lds, hipStream_t st)
 {
@@ -527,33 +691,28 @@ static hipError_t launch(const Config &c, const KArgs &a, int grid, size_t lds, 
 
 static int upload(Plan *pl);
 
-static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *sbus, const double *v0,
-               double tol, int32_t max_iter, const pf_solve_opts *opts, void *workspace,
-               size_t workspace_bytes, int mode, double *v_out, int32_t *iters_out, uint8_t *conv_out,
-               int8_t *status_out, double *aux, double *aux2, void *stream)
+// Validates a solve's arguments and fills its kernel arguments (shared by pf_solve_batch,
+// the single-step entry points and the queue).
+static int make_args(Plan *pl, const Config &c, int32_t batch, const double *ybus, const double *sbus,
+                     const double *v0, double tol, int32_t max_iter, void *workspace, size_t workspace_bytes,
+                     int mode, double *v_out, int32_t *iters_out, uint8_t *conv_out, int8_t *status_out,
+                     double *aux, double *aux2, KArgs &a, int &ntiles, size_t &lds)
 {
-    Plan *pl = reinterpret_cast<Plan *>(plan_h);
-    if (!pl) { set_error("null plan"); return PF_EINVAL; }
-    if (batch < 0) { set_error("negative batch"); return PF_EINVAL; }
-    if (batch == 0) return PF_OK;
     const HostPlan &h = pl->h;
-    Config c;
-    std::string err;
-    if (!resolve_config(h, opts, c, err)) { set_error(err); return PF_EINVAL; }
     if (!ybus || !sbus || !v0) { set_error("null input pointer"); return PF_EINVAL; }
     if (mode == MODE_SOLVE && (!v_out || !iters_out || !conv_out)) { set_error("null output pointer"); return PF_EINVAL; }
     if (mode != MODE_SOLVE && !aux) { set_error("null output pointer"); return PF_EINVAL; }
     if (mode == MODE_MISMATCH && !aux2) { set_error("null output pointer"); return PF_EINVAL; }
     if (mode == MODE_SOLVE && (max_iter < 0 || !(tol >= 0.0))) { set_error("invalid tol or max_iter"); return PF_EINVAL; }
     const TileLayout L = tile_layout(h, c);
-    const int ntiles = (batch + c.tile - 1) / c.tile;
+    ntiles = (batch + c.tile - 1) / c.tile;
     const size_t need = L.bytes * (size_t)ntiles;
     if (!workspace || workspace_bytes < need) {
         set_error("workspace too small: need " + std::to_string(need) + " bytes");
         return PF_EINVAL;
     }
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) { set_error("workspace must be 256-byte aligned"); return PF_EINVAL; }
-    const size_t lds = lds_bytes(h, c);
+    lds = lds_bytes(h, c);
     if (lds > kLdsLimit) {
         set_error("longest LU column needs " + std::to_string(lds) + " B of LDS; use a smaller tile or fewer waves");
         return PF_EINVAL;
@@ -567,7 +726,6 @@ static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *
         set_error("the current device differs from the plan's device");
         return PF_EDEVICE;
     }
-    KArgs a;
     std::memset(&a, 0, sizeof(a));
     a.p = pl->d;
     a.perm = pl->perm_dev;
@@ -575,8 +733,31 @@ static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *
     a.tol = tol; a.max_iter = max_iter; a.batch = batch; a.mode = mode;
     a.ws = reinterpret_cast<char *>(workspace);
     a.tile_bytes = L.bytes; a.off_y = L.off_y; a.off_vec = L.off_vec;
+    a.sched = c.schedule;
+    a.tsz = c.tile;
     a.v_out = v_out; a.iters_out = iters_out; a.conv_out = conv_out; a.status_out = status_out;
     a.aux_out = aux; a.aux2_out = aux2;
+    return PF_OK;
+}
+
+static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *sbus, const double *v0,
+               double tol, int32_t max_iter, const pf_solve_opts *opts, void *workspace,
+               size_t workspace_bytes, int mode, double *v_out, int32_t *iters_out, uint8_t *conv_out,
+               int8_t *status_out, double *aux, double *aux2, void *stream)
+{
+    Plan *pl = reinterpret_cast<Plan *>(plan_h);
+    if (!pl) { set_error("null plan"); return PF_EINVAL; }
+    if (batch < 0) { set_error("negative batch"); return PF_EINVAL; }
+    if (batch == 0) return PF_OK;
+    Config c;
+    std::string err;
+    if (!resolve_config(pl->h, opts, c, err)) { set_error(err); return PF_EINVAL; }
+    KArgs a;
+    int ntiles = 0;
+    size_t lds = 0;
+    const int rc = make_args(pl, c, batch, ybus, sbus, v0, tol, max_iter, workspace, workspace_bytes, mode, v_out,
+                             iters_out, conv_out, status_out, aux, aux2, a, ntiles, lds);
+    if (rc != PF_OK) return rc;
     hipError_t e = launch(c, a, ntiles, lds, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) { set_error(std::string("kernel launch failed: ") + hipGetErrorString(e)); return PF_EDEVICE; }
     return PF_OK;
@@ -607,6 +788,7 @@ static int upload(Plan *pl)
     const size_t o_bp = off.add(h.bs_ptr), o_bpos = off.add(h.bs_pos), o_bcol = off.add(h.bs_col);
     const size_t o_pe = off.add(h.bus_peq), o_qe = off.add(h.bus_qeq), o_pu = off.add(h.pos_upd);
     const size_t o_perm = off.add(h.perm), o_pp = off.add(h.panel_ptr);
+    const size_t o_ls = off.add(h.lu_seq), o_bsq = off.add(h.bs_seq);
     std::vector<char> host(off.bytes, 0);
     auto put = [&](size_t o, const auto &v) {
         if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * sizeof(v[0]));
@@ -617,6 +799,7 @@ static int upload(Plan *pl)
     put(o_lc, h.lev_cols); put(o_blp, h.bs_lev_ptr); put(o_blr, h.bs_lev_rows); put(o_bp, h.bs_ptr);
     put(o_bpos, h.bs_pos); put(o_bcol, h.bs_col); put(o_pe, h.bus_peq); put(o_qe, h.bus_qeq);
     put(o_pu, h.pos_upd); put(o_perm, h.perm); put(o_pp, h.panel_ptr);
+    put(o_ls, h.lu_seq); put(o_bsq, h.bs_seq);
     void *dm = nullptr;
     if (hipMalloc(&dm, off.bytes) != hipSuccess) { set_error("hipMalloc of the plan failed"); return PF_ENOMEM; }
     if (hipMemcpy(dm, host.data(), off.bytes, hipMemcpyHostToDevice) != hipSuccess) {
@@ -642,9 +825,249 @@ static int upload(Plan *pl)
     d.bus_peq = (const int32_t *)(D + o_pe); d.bus_qeq = (const int32_t *)(D + o_qe); d.pos_upd = (const int32_t *)(D + o_pu);
     pl->perm_dev = (const int32_t *)(D + o_perm);
     d.panel_ptr = (const int32_t *)(D + o_pp);
+    d.lu_seq = (const int32_t *)(D + o_ls);
+    d.bs_seq = (const int32_t *)(D + o_bsq);
     d.n_panels = (int)h.panel_ptr.size() - 1;
     return PF_OK;
 }
+
+
+// ------------------------------------------------------------------ pattern hash
+// FNV-1a over the sizes, bus types, Ybus pattern and elimination order: two plans with
+// the same hash run the same schedule, so a tuned configuration can be reused.
+static uint64_t pattern_hash(const HostPlan &h)
+{
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t bytes) {
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < bytes; i++) { x ^= c[i]; x *= 1099511628211ull; }
+    };
+    mix(&h.n, sizeof(h.n));
+    mix(&h.N, sizeof(h.N));
+    mix(h.bus_type.data(), h.bus_type.size());
+    mix(h.yrp.data(), h.yrp.size() * sizeof(int32_t));
+    mix(h.yci.data(), h.yci.size() * sizeof(int32_t));
+    mix(h.perm.data(), h.perm.size() * sizeof(int32_t));
+    return x;
+}
+
+// ------------------------------------------------------------------ multi-pattern queue
+// Work items (a plan, its instances, inputs, outputs and launch configuration) are grouped
+// by precision and workgroup size; each group becomes one persistent kernel whose
+// workgroups pop tiles from the group's counter.  Inside a group the items are ordered by
+// decreasing cost per tile, so the largest tiles start first and the small ones fill the
+// tail.  The reset kernel and the group kernels form one graph, built on the first run and
+// replayed afterwards.
+struct QueueItem {
+    Plan *plan;
+    Config c;
+    int32_t batch;
+    const double *ybus, *sbus, *v0;
+    double tol;
+    int32_t max_iter;
+    double *v_out;
+    int32_t *iters_out;
+    uint8_t *conv_out;
+    int8_t *status_out;
+    unsigned long long *ticks_out;
+};
+
+struct Queue {
+    int device = -1;
+    std::vector<QueueItem> items;
+    bool built = false;
+    void *dev_mem = nullptr;
+    size_t ws_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t n_tiles = 0, n_instances = 0;
+    std::vector<int> grid;
+    double clock_hz = 0.0;
+};
+
+static void queue_release(Queue *q)
+{
+    if (q->exec) (void)hipGraphExecDestroy(q->exec);
+    if (q->graph) (void)hipGraphDestroy(q->graph);
+    if (q->dev_mem) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(q->dev_mem);
+    }
+    q->exec = nullptr; q->graph = nullptr; q->dev_mem = nullptr;
+    q->built = false;
+    q->grid.clear();
+}
+
+static double tile_cost(const QueueItem &it)
+{
+    const HostPlan &h = it.plan->h;
+    const double rs = it.c.precision == PF_FP32_LU ? 4.0 : 8.0;
+    return (4.0 * rs * h.col_ptr[h.N] + 80.0 * h.n + 32.0 * h.N) * it.c.tile;
+}
+
+static int queue_build(Queue *q)
+{
+    queue_release(q);
+    // groups keyed by (precision, waves), items ordered by cost per tile
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (int i = 0; i < (int)q->items.size(); i++)
+        if (q->items[i].batch > 0) groups[{q->items[i].c.precision, q->items[i].c.waves}].push_back(i);
+    for (auto &g : groups)
+        std::stable_sort(g.second.begin(), g.second.end(),
+                         [&](int x, int y) { return tile_cost(q->items[x]) > tile_cost(q->items[y]); });
+    const int ng = (int)groups.size();
+    int nitems = 0;
+    for (auto &g : groups) nitems += (int)g.second.size();
+
+    // device block: KArgs[nitems] | prefix[nitems + ng] | counters[ng] | t0 | workspaces
+    const size_t off_prefix = align256(sizeof(KArgs) * (size_t)std::max(nitems, 1));
+    const size_t off_counter = off_prefix + align256(sizeof(int) * (size_t)(nitems + ng + 1));
+    const size_t off_t0 = off_counter + align256(sizeof(int) * (size_t)std::max(ng, 1));
+    size_t off_ws = off_t0 + 256;
+    std::vector<size_t> ws_off(q->items.size(), 0);
+    std::vector<int> ntiles(q->items.size(), 0);
+    for (auto &g : groups)
+        for (int i : g.second) {
+            const QueueItem &it = q->items[i];
+            const TileLayout L = tile_layout(it.plan->h, it.c);
+            ntiles[i] = (it.batch + it.c.tile - 1) / it.c.tile;
+            ws_off[i] = off_ws;
+            off_ws += align256(L.bytes * (size_t)ntiles[i]);
+        }
+    const size_t total = off_ws;
+    if (hipMalloc(&q->dev_mem, total) != hipSuccess) {
+        (void)hipGetLastError();
+        q->dev_mem = nullptr;
+        set_error("out of device memory for the queue (" + std::to_string(total) + " bytes)");
+        return PF_ENOMEM;
+    }
+    char *base = static_cast<char *>(q->dev_mem);
+    q->ws_bytes = total - (off_t0 + 256);
+    auto *d_t0 = reinterpret_cast<unsigned long long *>(base + off_t0);
+    int *d_counter = reinterpret_cast<int *>(base + off_counter);
+    int *d_prefix = reinterpret_cast<int *>(base + off_prefix);
+    auto *d_items = reinterpret_cast<KArgs *>(base);
+
+    std::vector<KArgs> h_items(std::max(nitems, 1));
+    std::vector<int> h_prefix(nitems + ng + 1, 0);
+    struct GroupLaunch { const void *fn; int first, count, prefix_at, waves; size_t lds; };
+    std::vector<GroupLaunch> gl;
+    int pos = 0, pre = 0;
+    q->n_tiles = 0; q->n_instances = 0;
+    for (auto &g : groups) {
+        GroupLaunch L{queue_kernel(g.first.first, g.first.second), pos, (int)g.second.size(), pre,
+                      g.first.second, 0};
+        int acc = 0;
+        for (int i : g.second) {
+            const QueueItem &it = q->items[i];
+            int nt = 0;
+            size_t lds = 0;
+            KArgs &a = h_items[pos];
+            const int rc = make_args(it.plan, it.c, it.batch, it.ybus, it.sbus, it.v0, it.tol, it.max_iter,
+                                     base + ws_off[i], (size_t)ntiles[i] * tile_layout(it.plan->h, it.c).bytes,
+                                     MODE_SOLVE, it.v_out, it.iters_out, it.conv_out, it.status_out, nullptr,
+                                     nullptr, a, nt, lds);
+            if (rc != PF_OK) { queue_release(q); return rc; }
+            a.done_ticks = it.ticks_out;
+            a.t0 = d_t0;
+            L.lds = std::max(L.lds, lds);
+            h_prefix[pre++] = acc;
+            acc += nt;
+            pos++;
+            q->n_instances += it.batch;
+        }
+        h_prefix[pre++] = acc;
+        q->n_tiles += acc;
+        gl.push_back(L);
+    }
+    hipError_t e = hipMemcpy(base, h_items.data(), sizeof(KArgs) * (size_t)nitems, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(d_prefix, h_prefix.data(), sizeof(int) * h_prefix.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        set_error(std::string("queue upload failed: ") + hipGetErrorString(e));
+        queue_release(q);
+        return PF_EDEVICE;
+    }
+
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, q->device);
+    auto fail = [&](const std::string &what, hipError_t err) {
+        set_error(what + ": " + hipGetErrorString(err));
+        queue_release(q);
+        return PF_EDEVICE;
+    };
+    if ((e = hipGraphCreate(&q->graph, 0)) != hipSuccess) return fail("graph creation failed", e);
+    hipGraphNode_t reset;
+    {
+        int ngv = ng;
+        void *args[] = {&d_counter, &ngv, &d_t0};
+        hipKernelNodeParams kp{};
+        kp.func = reinterpret_cast<void *>(queue_reset_kernel);
+        kp.gridDim = dim3(1);
+        kp.blockDim = dim3(64);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        if ((e = hipGraphAddKernelNode(&reset, q->graph, nullptr, 0, &kp)) != hipSuccess)
+            return fail("graph reset node failed", e);
+    }
+    for (int gi = 0; gi < ng; gi++) {
+        const GroupLaunch &L = gl[gi];
+        hipFuncAttributes fa{};
+        if ((e = hipFuncGetAttributes(&fa, L.fn)) != hipSuccess) return fail("kernel attributes", e);
+        if (fa.sharedSizeBytes + L.lds > 160 * 1024) {
+            set_error("queue group needs " + std::to_string(fa.sharedSizeBytes + L.lds) + " B of LDS");
+            queue_release(q);
+            return PF_EINVAL;
+        }
+        if (L.lds > 64 * 1024 &&
+            (e = hipFuncSetAttribute(L.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(160 * 1024 - fa.sharedSizeBytes))) != hipSuccess)
+            return fail("LDS attribute", e);
+        int per_cu = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, L.fn, L.waves * 64, L.lds)) != hipSuccess)
+            return fail("occupancy query", e);
+        if (per_cu < 1) {
+            set_error("queue kernel cannot be resident with its LDS");
+            queue_release(q);
+            return PF_EINVAL;
+        }
+        const int tiles = h_prefix[L.prefix_at + L.count];
+        const int grid = std::max(1, std::min(tiles, per_cu * std::max(cus, 1)));
+        q->grid.push_back(grid);
+        const KArgs *items_p = d_items + L.first;
+        const int *prefix_p = d_prefix + L.prefix_at;
+        int cnt = L.count;
+        int *counter_p = d_counter + gi;
+        void *args[] = {&items_p, &prefix_p, &cnt, &counter_p};
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void *>(L.fn);
+        kp.gridDim = dim3(grid);
+        kp.blockDim = dim3(L.waves * 64);
+        kp.sharedMemBytes = (unsigned)L.lds;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        if ((e = hipGraphAddKernelNode(&node, q->graph, &reset, 1, &kp)) != hipSuccess)
+            return fail("graph kernel node failed", e);
+    }
+    if ((e = hipGraphInstantiate(&q->exec, q->graph, nullptr, nullptr, 0)) != hipSuccess)
+        return fail("graph instantiation failed", e);
+    q->built = true;
+    return PF_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+struct TuneKey {
+    uint64_t hash;
+    int device, precision, waves, batch;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(hash, device, precision, waves, batch) < std::tie(o.hash, o.device, o.precision, o.waves, o.batch);
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, std::pair<pf_solve_opts, double>> g_tune_cache;
 
 }  // namespace pf
 
@@ -708,6 +1131,7 @@ int pf_plan_info(pf_plan plan, pf_plan_info_t *o)
     // refactor 2b nnz_lu, substitutions b nnz_lu + 16N, update 8N+32n
     o->bytes_iter_fp64 = 4 * 8 * (int64_t)o->nnz_lu + 80 * (int64_t)h.n + 32 * (int64_t)h.N;
     o->bytes_iter_fp32 = 4 * 4 * (int64_t)o->nnz_lu + 80 * (int64_t)h.n + 32 * (int64_t)h.N;
+    o->pattern_hash = pattern_hash(h);
     return PF_OK;
 }
 
@@ -774,6 +1198,202 @@ int pf_eval_step(pf_plan plan, int32_t batch, const double *ybus, const double *
 {
     return run(plan, batch, ybus, sbus, v, 0.0, 0, opts, workspace, workspace_bytes, MODE_STEP,
                nullptr, nullptr, nullptr, nullptr, dx_out, nullptr, stream);
+}
+
+int pf_queue_create(pf_queue *out)
+{
+    if (!out) { set_error("null output queue pointer"); return PF_EINVAL; }
+    *out = nullptr;
+    Queue *q = new (std::nothrow) Queue();
+    if (!q) { set_error("out of host memory"); return PF_ENOMEM; }
+    if (hipGetDevice(&q->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete q;
+        set_error("no current device");
+        return PF_EDEVICE;
+    }
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, q->device) != hipSuccess) {
+        (void)hipGetLastError();
+        khz = 0;
+    }
+    q->clock_hz = 1e3 * khz;
+    *out = reinterpret_cast<pf_queue>(q);
+    return PF_OK;
+}
+
+int pf_queue_add(pf_queue queue, pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
+                 const double *v0, double tol, int32_t max_iter, const pf_solve_opts *opts, double *v_out,
+                 int32_t *iters_out, uint8_t *converged_out, int8_t *status_out, uint64_t *done_ticks_out)
+{
+    Queue *q = reinterpret_cast<Queue *>(queue);
+    Plan *pl = reinterpret_cast<Plan *>(plan);
+    if (!q || !pl) { set_error("null queue or plan"); return PF_EINVAL; }
+    if (batch < 0) { set_error("negative batch"); return PF_EINVAL; }
+    if (max_iter < 0 || !(tol >= 0.0)) { set_error("invalid tol or max_iter"); return PF_EINVAL; }
+    if (batch == 0) return PF_OK;     // nothing to solve: the item is not kept
+    if (!ybus || !sbus || !v0 || !v_out || !iters_out || !converged_out) { set_error("null pointer"); return PF_EINVAL; }
+    if (pl->dev_mem && pl->device != q->device) { set_error("plan and queue are on different devices"); return PF_EDEVICE; }
+    Config c;
+    std::string err;
+    if (!resolve_config(pl->h, opts, c, err)) { set_error(err); return PF_EINVAL; }
+    if (lds_bytes(pl->h, c) > kLdsLimit) { set_error("configuration does not fit in LDS"); return PF_EINVAL; }
+    QueueItem it{pl, c, batch, ybus, sbus, v0, tol, max_iter, v_out, iters_out, converged_out, status_out,
+                 reinterpret_cast<unsigned long long *>(done_ticks_out)};
+    try {
+        q->items.push_back(it);
+    } catch (const std::bad_alloc &) {
+        set_error("out of host memory");
+        return PF_ENOMEM;
+    }
+    q->built = false;
+    return PF_OK;
+}
+
+int pf_queue_run(pf_queue queue, void *stream)
+{
+    Queue *q = reinterpret_cast<Queue *>(queue);
+    if (!q) { set_error("null queue"); return PF_EINVAL; }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != q->device) {
+        set_error("the current device differs from the queue's device");
+        return PF_EDEVICE;
+    }
+    if (q->items.empty()) return PF_OK;
+    if (!q->built) {
+        const int rc = queue_build(q);
+        if (rc != PF_OK) return rc;
+    }
+    if (q->n_tiles == 0) return PF_OK;
+    const hipError_t e = hipGraphLaunch(q->exec, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) { set_error(std::string("graph launch failed: ") + hipGetErrorString(e)); return PF_EDEVICE; }
+    return PF_OK;
+}
+
+int pf_queue_info(pf_queue queue, pf_queue_info_t *o)
+{
+    Queue *q = reinterpret_cast<Queue *>(queue);
+    if (!q || !o) { set_error("null argument"); return PF_EINVAL; }
+    std::memset(o, 0, sizeof(*o));
+    o->n_items = (int32_t)q->items.size();
+    o->built = q->built ? 1 : 0;
+    o->n_groups = (int32_t)q->grid.size();
+    for (int i = 0; i < (int)q->grid.size() && i < 6; i++) o->grid[i] = q->grid[i];
+    o->n_tiles = q->n_tiles;
+    o->n_instances = q->n_instances;
+    o->workspace_bytes = q->ws_bytes;
+    o->wall_clock_hz = q->clock_hz;
+    return PF_OK;
+}
+
+void pf_queue_destroy(pf_queue queue)
+{
+    Queue *q = reinterpret_cast<Queue *>(queue);
+    if (!q) return;
+    queue_release(q);
+    delete q;
+}
+
+int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus, const double *v0, double tol,
+            int32_t max_iter, int32_t precision, int32_t waves, int32_t reps, int32_t flags,
+            pf_solve_opts *best_out, double *best_ms_out, void *stream)
+{
+    Plan *pl = reinterpret_cast<Plan *>(plan);
+    if (!pl || !best_out) { set_error("null plan or output"); return PF_EINVAL; }
+    if (batch <= 0 || reps <= 0) { set_error("batch and reps must be positive"); return PF_EINVAL; }
+    if (!ybus || !sbus || !v0) { set_error("null input pointer"); return PF_EINVAL; }
+    if (precision != PF_FP64 && precision != PF_FP32_LU) { set_error("unknown precision"); return PF_EINVAL; }
+    if (waves != 0 && waves != 2 && waves != 4 && waves != 8) { set_error("waves must be 0, 2, 4 or 8"); return PF_EINVAL; }
+    if (max_iter < 0 || !(tol >= 0.0)) { set_error("invalid tol or max_iter"); return PF_EINVAL; }
+    if (!pl->dev_mem) {
+        const int rcu = upload(pl);
+        if (rcu != PF_OK) return rcu;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != pl->device) {
+        set_error("the current device differs from the plan's device");
+        return PF_EDEVICE;
+    }
+    const TuneKey key{pattern_hash(pl->h), dev, precision, waves, batch};
+    if (!(flags & PF_TUNE_FORCE)) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto f = g_tune_cache.find(key);
+        if (f != g_tune_cache.end()) {
+            *best_out = f->second.first;
+            if (best_ms_out) *best_ms_out = f->second.second;
+            return PF_OK;
+        }
+    }
+    // candidate configurations that fit in LDS
+    std::vector<pf_solve_opts> cand;
+    const int tiles64[] = {4, 8, 16}, tiles32[] = {8, 16, 32}, wv[] = {2, 4, 8};
+    for (int ti = 0; ti < 3; ti++)
+        for (int w : wv) {
+            if (waves && w != waves) continue;
+            for (int sc = 0; sc < 2; sc++) {
+                pf_solve_opts o{};
+                o.precision = precision;
+                o.tile = precision == PF_FP64 ? tiles64[ti] : tiles32[ti];
+                o.waves = w;
+                o.schedule = sc;
+                Config c;
+                std::string err;
+                if (resolve_config(pl->h, &o, c, err) && lds_bytes(pl->h, c) <= kLdsLimit) cand.push_back(o);
+            }
+        }
+    if (cand.empty()) { set_error("no configuration fits in LDS"); return PF_EINVAL; }
+    size_t ws = 0;
+    for (auto &o : cand) ws = std::max(ws, pf_workspace_bytes(plan, batch, &o));
+    const size_t n = (size_t)pl->h.n;
+    const size_t out_bytes = align256(sizeof(double) * 2 * n * batch) + align256(sizeof(int32_t) * batch) +
+                             align256((size_t)batch) + align256((size_t)batch);
+    void *mem = nullptr;
+    if (hipMalloc(&mem, ws + out_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("out of device memory for tuning");
+        return PF_ENOMEM;
+    }
+    char *m = static_cast<char *>(mem);
+    double *v_out = reinterpret_cast<double *>(m + ws);
+    int32_t *it_out = reinterpret_cast<int32_t *>(m + ws + align256(sizeof(double) * 2 * n * batch));
+    uint8_t *cv_out = reinterpret_cast<uint8_t *>(it_out) + align256(sizeof(int32_t) * batch);
+    int8_t *st_out = reinterpret_cast<int8_t *>(cv_out + align256((size_t)batch));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = PF_OK;
+    double best = 1e300;
+    pf_solve_opts best_o = cand[0];
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        set_error("event creation failed");
+        rc = PF_EDEVICE;
+    }
+    for (size_t ci = 0; rc == PF_OK && ci < cand.size(); ci++) {
+        const pf_solve_opts &o = cand[ci];
+        rc = pf_solve_batch(plan, batch, ybus, 0, sbus, v0, tol, max_iter, &o, m, ws, v_out, it_out, cv_out, st_out,
+                            stream);
+        if (rc != PF_OK) break;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps && rc == PF_OK; r++)
+            rc = pf_solve_batch(plan, batch, ybus, 0, sbus, v0, tol, max_iter, &o, m, ws, v_out, it_out, cv_out,
+                                st_out, stream);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) { set_error("tuning run failed"); rc = PF_EDEVICE; break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double per = ms / reps;
+        if (per < best) { best = per; best_o = o; }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(mem);
+    if (rc != PF_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = {best_o, best};
+    }
+    *best_out = best_o;
+    if (best_ms_out) *best_ms_out = best;
+    return PF_OK;
 }
 
 void pf_plan_destroy(pf_plan plan)

@@ -1,0 +1,136 @@
+"""Warm-start network kernels on the GPU against the FP64 numpy reference (oracle/mlp.py),
+and the gain of the trained network over flat start.
+
+Bars:
+  * GEMM (MFMA, BF16 operands, FP32 accumulation): |C - C_ref| <= 1e-5 * (|A| |B|)_ij + 1e-6
+    elementwise, C_ref computed in FP64 from the same BF16-rounded operands;
+  * gradients of a whole network: relative Frobenius error <= 1e-2 per weight and bias
+    (BF16 activations and dZ between layers, FP32 accumulation);
+  * one Adam step: matches the reference to FP32 rounding (rel 1e-5);
+  * warm start (parity unpinned for its size: no paper figure exists): on held-out scenarios
+    the mean iteration count is below flat start's, every instance converges, and the
+    solutions equal the flat-start ones within 1e-6.
+"""
+import numpy as np
+import pytest
+
+import gridgen as gg
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2101_02270_amd as pf  # noqa: E402
+from paper_2101_02270_amd import warmstart as ws  # noqa: E402
+
+DEV = "cuda"
+
+
+def to_bf16_tensor(a):
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return torch.from_numpy(u.view(np.int16).copy()).to(DEV)
+
+
+def from_bf16_tensor(t):
+    u = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+def gemm(M, N, K, A, B, ta, tb, bias=None, gelu=False):
+    z = torch.empty((M, N), dtype=torch.float32, device=DEV)
+    af = torch.empty((M, N), dtype=torch.float32, device=DEV)
+    ab = torch.empty((M, N), dtype=torch.int16, device=DEV)
+    lib = pf.lib()
+    rc = lib.pf_mlp_gemm(M, N, K, int(ta), int(tb), A.data_ptr(), B.data_ptr(),
+                         bias.data_ptr() if bias is not None else None, int(gelu), z.data_ptr(),
+                         ab.data_ptr(), af.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    torch.cuda.synchronize()
+    return z.cpu().numpy().astype(np.float64), af.cpu().numpy().astype(np.float64), from_bf16_tensor(ab)
+
+
+@pytest.mark.parametrize("M,N,K", [(64, 64, 32), (37, 70, 45), (130, 17, 300), (1, 1, 1), (200, 129, 64)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1)])
+def test_gemm_against_reference(M, N, K, ta, tb):
+    rng = np.random.default_rng(M * 7 + N * 13 + K)
+    a = rng.normal(size=(K, M) if ta else (M, K))
+    b = rng.normal(size=(N, K) if tb else (K, N))
+    ar, br = mlp.bf16_round(a), mlp.bf16_round(b)
+    A, B = to_bf16_tensor(a), to_bf16_tensor(b)
+    bias = rng.normal(size=N).astype(np.float32)
+    z, act, act_b = gemm(M, N, K, A, B, ta, tb, torch.from_numpy(bias).to(DEV), gelu=True)
+    opa = ar.T if ta else ar
+    opb = br.T if tb else br
+    ref = opa @ opb + bias.astype(np.float64)
+    bound = 1e-5 * (np.abs(opa) @ np.abs(opb)) + 1e-6
+    assert np.all(np.abs(z - ref) <= bound)
+    assert np.allclose(act, mlp.gelu(z), rtol=1e-5, atol=1e-6)
+    assert np.allclose(act_b, mlp.bf16_round(mlp.gelu(z).astype(np.float32)), rtol=0, atol=1e-2 * np.abs(act).max())
+
+
+def test_network_gradients_and_adam_against_reference():
+    # a small network with the same code path as the warm-start net
+    bt = np.array([gg.REF] + [gg.PQ] * 12 + [gg.PV] * 5, np.int8)   # 17 feature buses -> 34 in/out
+    net = ws.WarmStartNet(bt, hidden=(48, 40, 56), seed=1)
+    rng = np.random.default_rng(2)
+    Bt = 37
+    x = rng.normal(size=(Bt, net.dims[0]))
+    y = rng.normal(size=(Bt, net.dims[-1])).astype(np.float32)
+    xb = to_bf16_tensor(x)
+    W0 = [w.cpu().numpy().astype(np.float64) for w in net.W]
+    b0 = [b.cpu().numpy().astype(np.float64) for b in net.b]
+    Wr = [mlp.bf16_round(w) for w in W0]
+    net.train_step(xb, torch.from_numpy(y).to(DEV), lr=1e-3)
+    torch.cuda.synchronize()
+    out, cache = mlp.forward(mlp.bf16_round(x), Wr, b0)
+    _, dout = mlp.mse(out, y.astype(np.float64))
+    grads = mlp.backward(dout, Wr, cache)
+    for l in range(len(W0)):
+        dW = net.last_grads[l][0].cpu().numpy()
+        db = net.last_grads[l][1].cpu().numpy()
+        assert np.linalg.norm(dW - grads[l][0]) <= 1e-2 * np.linalg.norm(grads[l][0]), l
+        assert np.linalg.norm(db - grads[l][1]) <= 1e-2 * np.linalg.norm(grads[l][1]) + 1e-12, l
+        # one Adam step from zero moments on the GPU's own gradient
+        w_ref, _, _ = mlp.adam_step(W0[l], dW.astype(np.float64), np.zeros_like(W0[l]), np.zeros_like(W0[l]), 1)
+        assert np.allclose(net.W[l].cpu().numpy(), w_ref, rtol=1e-5, atol=1e-7), l
+
+
+def test_warm_start_reduces_iterations():
+    g = gg.grid("c4_100bus")
+    yb = gg.ybus(g)
+    plan = pf.Plan.from_ybus(yb, g.bus_type)
+    tr = gg.make_scenarios(g, 6000, 501, "mc")
+    ev = gg.make_scenarios(g, 1000, 502, "mc")
+    y = torch.from_numpy(yb.val).to(DEV)
+    s_tr = torch.from_numpy(tr.sbus).to(DEV)
+    v_tr = torch.from_numpy(tr.v0).to(DEV)
+    sol = pf.solve_batch(plan, y, s_tr, v_tr)
+    ok = sol.converged.cpu().numpy().astype(bool)
+    net = ws.WarmStartNet(g.bus_type, hidden=(128, 128, 128), seed=0)
+    mu_x, sd_x = ws.feature_stats(net, tr.sbus[ok], tr.v0[ok])
+    Y = ws.targets_from_solution(net, sol.v.cpu().numpy()[ok])
+    mu_y, sd_y = ws.target_stats(Y)
+    net.set_normalization(mu_x, sd_x, mu_y, sd_y)
+    idx = torch.from_numpy(np.flatnonzero(ok)).to(DEV)
+    X = net.features(s_tr.index_select(0, idx).contiguous(), v_tr.index_select(0, idx).contiguous())
+    Yn = torch.from_numpy(((Y - mu_y) / sd_y).astype(np.float32)).to(DEV)
+    n_train = int(0.9 * X.shape[0])
+    rep = net.fit(X, Yn, n_train, epochs=12, batch=128, lr=2e-3)
+    assert rep.val_loss[-1] < 0.2 * rep.val_loss[0]
+    s_ev = torch.from_numpy(ev.sbus).to(DEV)
+    v_ev = torch.from_numpy(ev.v0).to(DEV)
+    flat = pf.solve_batch(plan, y, s_ev, v_ev)
+    warm, n_fb = ws.solve_with_warm_start(plan, net, y, s_ev, v_ev)
+    fi = flat.iters.cpu().numpy(); wi = warm.iters.cpu().numpy()
+    fc = flat.converged.cpu().numpy().astype(bool); wc = warm.converged.cpu().numpy().astype(bool)
+    print(f"\nflat start mean iterations {fi[fc].mean():.3f}, warm start {wi[wc].mean():.3f}, "
+          f"fallbacks {n_fb}, train {rep.seconds:.1f} s")
+    assert wc[fc].all()
+    assert wi[fc].mean() < fi[fc].mean()
+    dv = np.abs(warm.v.cpu().numpy()[fc] - flat.v.cpu().numpy()[fc]).max()
+    assert dv <= 1e-6, dv

@@ -1,0 +1,166 @@
+"""Multi-pattern persistent queue and autotuner on the GPU.
+
+Bars:
+  * every queued instance equals its single-pattern pf_solve_batch result with the same
+    configuration: identical iteration counts, flags and statuses, voltages within 1e-12
+    (the same kernel body and schedule; only the launch differs);
+  * a replay after the inputs changed in place gives the new inputs' results, and items
+    whose inputs did not change repeat their previous results exactly;
+  * completion ticks are positive and no later than the host-measured run time;
+  * the tuner returns a configuration that fits the plan, caches it, and the solve with it
+    agrees with the default configuration's (different rounding order only: 1e-10).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import gridgen as gg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2101_02270_amd as pf  # noqa: E402
+
+DEV = "cuda"
+_PLANS = {}
+
+
+def system(name):
+    if name not in _PLANS:
+        g = gg.grid(name)
+        yb = gg.ybus(g)
+        _PLANS[name] = (g, yb, pf.Plan.from_ybus(yb, g.bus_type), torch.from_numpy(yb.val).to(DEV))
+    return _PLANS[name]
+
+
+def inputs(name, count, seed):
+    g, _, _, _ = system(name)
+    sc = gg.make_scenarios(g, max(count, 1), seed, "mc")
+    s = torch.from_numpy(np.ascontiguousarray(sc.sbus[:count])).to(DEV)
+    v = torch.from_numpy(np.ascontiguousarray(sc.v0[:count])).to(DEV)
+    return s, v
+
+
+ITEMS = [
+    ("c4_100bus", 300, dict(precision=pf.PF_FP64, tile=8, waves=4, schedule=0)),
+    ("c4_1000bus", 100, dict(precision=pf.PF_FP64, tile=4, waves=4, schedule=1)),
+    ("c1_1350bus", 37, dict(precision=pf.PF_FP64, tile=16, waves=4, schedule=0)),
+    ("c0_14bus", 64, dict(precision=pf.PF_FP32_LU, tile=32, waves=2, schedule=0)),
+    ("c4_100bus", 50, dict(precision=pf.PF_FP32_LU, tile=8, waves=8, schedule=1)),
+]
+
+
+def assert_same(a, b, exact=False):
+    torch.cuda.synchronize()
+    assert torch.equal(a.iters, b.iters)
+    assert torch.equal(a.converged, b.converged)
+    assert torch.equal(a.status, b.status)
+    dv = (a.v - b.v).abs().max().item() if a.v.numel() else 0.0
+    assert dv == 0.0 if exact else dv <= 1e-12, dv
+
+
+def test_queue_matches_single_pattern_solves():
+    q = pf.Queue()
+    data, outs = [], []
+    for k, (name, count, opts) in enumerate(ITEMS):
+        _, _, plan, y = system(name)
+        s, v = inputs(name, count, 700 + k)
+        data.append((plan, y, s, v, opts))
+        outs.append(q.add(plan, y, s, v, **opts))
+    # an empty item is accepted and contributes nothing
+    _, _, plan0, y0 = system("c4_100bus")
+    s0, v0 = inputs("c4_100bus", 0, 1)
+    q.add(plan0, y0, s0, v0, precision=pf.PF_FP64, tile=8, waves=4)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    q.run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    info = q.info()
+    print(f"\nqueue info {info}, first run {elapsed * 1e3:.1f} ms (includes graph build)")
+    assert info["built"] == 1
+    assert info["n_groups"] == 3          # (FP64, 4 waves), (FP32-LU, 2), (FP32-LU, 8)
+    assert info["n_instances"] == sum(c for _, c, _ in ITEMS)
+    assert info["n_tiles"] == sum((c + o["tile"] - 1) // o["tile"] for _, c, o in ITEMS)
+    ref = []
+    for (plan, y, s, v, opts), out in zip(data, outs):
+        r = pf.solve_batch(plan, y, s, v, **opts)
+        assert_same(out, r)
+        ref.append(r)
+        assert bool(out.converged.all()), "synthetic scenarios all converge"
+    hz = info["wall_clock_hz"]
+    assert hz > 0
+    for out in outs:
+        tk = out.ticks.cpu().numpy()
+        assert (tk > 0).all()
+        assert tk.max() / hz <= elapsed + 1e-3
+
+    # replay after changing one item's loads in place: that item follows, the rest repeat
+    prev = [(o.v.clone(), o.iters.clone()) for o in outs]
+    plan, y, s, v, opts = data[1]
+    s.mul_(1.02)
+    q.run()
+    torch.cuda.synchronize()
+    assert_same(outs[1], pf.solve_batch(plan, y, s, v, **opts))
+    assert not torch.equal(outs[1].v, prev[1][0])
+    for k in (0, 2, 3, 4):
+        assert torch.equal(outs[k].v, prev[k][0]) and torch.equal(outs[k].iters, prev[k][1])
+    q.close()
+
+
+def test_queue_rebuilds_after_add():
+    q = pf.Queue()
+    _, _, plan, y = system("c4_100bus")
+    s, v = inputs("c4_100bus", 40, 11)
+    a = q.add(plan, y, s, v, precision=pf.PF_FP64, tile=8, waves=4)
+    q.run()
+    torch.cuda.synchronize()
+    assert q.info()["built"] == 1
+    s2, v2 = inputs("c4_100bus", 24, 12)
+    b = q.add(plan, y, s2, v2, precision=pf.PF_FP64, tile=4, waves=8)
+    assert q.info()["built"] == 0
+    q.run()
+    torch.cuda.synchronize()
+    assert q.info()["n_groups"] == 2
+    assert_same(a, pf.solve_batch(plan, y, s, v, precision=pf.PF_FP64, tile=8, waves=4))
+    assert_same(b, pf.solve_batch(plan, y, s2, v2, precision=pf.PF_FP64, tile=4, waves=8))
+    q.close()
+
+
+def test_queue_rejects_bad_items():
+    q = pf.Queue()
+    _, _, plan, y = system("c4_100bus")
+    s, v = inputs("c4_100bus", 8, 13)
+    with pytest.raises(pf.PfError):
+        q.add(plan, y, s, v, precision=pf.PF_FP64, tile=32, waves=4)      # FP32-only tile
+    with pytest.raises(pf.PfError):
+        q.add(plan, y, s, v, precision=pf.PF_FP64, tile=8, waves=3)
+    q.run()                                                                  # empty queue
+    q.close()
+
+
+def test_tuner_picks_valid_cached_configuration():
+    _, _, plan, y = system("c4_1000bus")
+    s, v = inputs("c4_1000bus", 256, 21)
+    t0 = time.perf_counter()
+    best, ms = pf.tune(plan, y, s, v, precision=pf.PF_FP64, reps=1)
+    t_tune = time.perf_counter() - t0
+    print(f"\ntuned {best} at {ms:.3f} ms in {t_tune:.2f} s")
+    assert best["precision"] == pf.PF_FP64
+    assert best["tile"] in (4, 8, 16) and best["waves"] in (2, 4, 8) and best["schedule"] in (0, 1)
+    assert ms > 0
+    t0 = time.perf_counter()
+    again, ms2 = pf.tune(plan, y, s, v, precision=pf.PF_FP64, reps=1)
+    assert again == best and ms2 == ms                       # served from the cache
+    assert time.perf_counter() - t0 < t_tune
+    fixed, _ = pf.tune(plan, y, s, v, precision=pf.PF_FP32_LU, waves=4, reps=1)
+    assert fixed["waves"] == 4 and fixed["tile"] in (8, 16, 32)
+    r = pf.solve_batch(plan, y, s, v, **best)
+    d = pf.solve_batch(plan, y, s, v)
+    torch.cuda.synchronize()
+    assert torch.equal(r.iters, d.iters)
+    assert (r.v - d.v).abs().max().item() <= 1e-10

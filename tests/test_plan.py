@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "pf.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pf_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(pf_[a-z_0-9]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -161,3 +161,26 @@ def test_plan_info_and_workspace():
     w32 = plan.workspace_bytes(10000, precision=pf.PF_FP32_LU)
     assert w64 > 10000 * info["nnz_lu"] * 8 and 0 < w32 < w64
     assert plan.workspace_bytes(10000, tile=7) == 0
+
+
+def test_pattern_hash_identifies_pattern_and_order():
+    g = gg.grid("c4_100bus")
+    yb = gg.ybus(g)
+    a = pf.Plan.from_ybus(yb, g.bus_type).info["pattern_hash"]
+    b = pf.Plan.from_ybus(yb, g.bus_type).info["pattern_hash"]
+    nat = pf.Plan.from_ybus(yb, g.bus_type, ordering=pf.PF_ORDER_NATURAL).info["pattern_hash"]
+    g2 = gg.grid("c4_1000bus")
+    other = pf.Plan.from_ybus(gg.ybus(g2), g2.bus_type).info["pattern_hash"]
+    bt = g.bus_type.copy()
+    bt[np.flatnonzero(bt == gg.PQ)[0]] = gg.PV
+    retyped = pf.Plan.from_ybus(yb, bt).info["pattern_hash"]
+    assert a == b and a != 0
+    assert len({a, nat, other, retyped}) == 4
+
+
+def test_queue_without_device_reports_error():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    with pytest.raises(pf.PfError):
+        pf.Queue()
