@@ -199,8 +199,8 @@ int pf_mlp_warm_v0(int32_t batch, int32_t n_bus, const float *out, const int32_t
 /*
  * Multi-pattern queue (an addition to the paper's method, which solves one grid per
  * launch): instances of several grids, each with its own plan and configuration, run in
- * one replayable graph.  Items that share precision and waves form one persistent kernel
- * whose workgroups take tiles from a device counter, largest cost per tile first.
+ * one replayable graph.  Items that share precision, tile and waves form one persistent
+ * kernel whose workgroups take tiles from a device counter, largest cost per tile first.
  *
  * pf_queue_create: an empty queue bound to the current device.
  * pf_queue_add: appends one item; arguments as in pf_solve_batch (opts selects precision,
@@ -220,7 +220,7 @@ typedef struct pf_queue_s *pf_queue;
 typedef struct {
     int32_t n_items, n_groups;     /* items added; persistent kernels of the built graph    */
     int32_t built;                 /* 1 when the graph is current                           */
-    int32_t grid[6];               /* workgroups of each persistent kernel                  */
+    int32_t grid[18];              /* workgroups of each persistent kernel                  */
     int64_t n_tiles, n_instances;  /* over all items                                       */
     size_t workspace_bytes;        /* device memory held by the queue                      */
     double wall_clock_hz;          /* rate of the done_ticks clock                          */
@@ -239,7 +239,7 @@ void pf_queue_destroy(pf_queue queue);
  * instances (the same arguments as pf_solve_batch) with reps timed solves after one
  * untimed one, and returns the fastest in best_out (its mean ms per solve in
  * best_ms_out, may be NULL).  waves = 0 tries every workgroup size, otherwise only that
- * one (so that tuned items of a queue share one persistent kernel).  Results are cached in
+ * one.  Results are cached in
  * the process, keyed by the plan's pattern hash, device, precision, waves and batch;
  * flags & PF_TUNE_FORCE re-times a cached key.  Allocates and frees its own device
  * buffers; synchronises with stream.

@@ -51,7 +51,7 @@ class _Opts(ctypes.Structure):
 
 class _QueueInfo(ctypes.Structure):
     _fields_ = [("n_items", ctypes.c_int32), ("n_groups", ctypes.c_int32), ("built", ctypes.c_int32),
-                ("grid", ctypes.c_int32 * 6), ("n_tiles", ctypes.c_int64),
+                ("grid", ctypes.c_int32 * 18), ("n_tiles", ctypes.c_int64),
                 ("n_instances", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
                 ("wall_clock_hz", ctypes.c_double)]
 

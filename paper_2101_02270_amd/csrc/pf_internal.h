@@ -16,6 +16,11 @@ struct JacDesc {
     int32_t p, i, k, kind;
 };
 
+// LU positions of the four Jacobian entries that one Ybus entry (i, k) produces.
+struct JPos {
+    int32_t pt, pv, qt, qv;
+};
+
 // One column-to-column update of the left-looking refactorization: column j receives
 // LU(r, j) -= LU(k, j) * LU(r, k) for every r in the L part of column k.
 struct Update {
@@ -23,6 +28,27 @@ struct Update {
     int32_t lbeg;       // absolute entry index of the first L entry of column k
     int32_t roff;       // offset into rel[]: relative target positions in column j
     int32_t k;          // source column
+};
+
+// Everything one refactorization panel needs, in processing order (one load per panel):
+// first column with the pair flag in bit 30, first entry and entry count of the column,
+// position of the diagonal inside it, the column's update range, and its working-column
+// slot and slot wait (see HostPlan::lslot).
+struct LuPanel {
+    int32_t j2, cs, cnt, dr, u0, u1, slot, wait;
+};
+
+// The same for back substitution: first row with the pair flag in bit 30, first entries of
+// the panel's columns, diagonal position, range of the last row's U entries in bs_col /
+// bs_pos, and the update target (bus * 2 + is |V|) of the first row.
+struct BsPanel {
+    int32_t j2, cs, cs1, dr, q0, q1, pu, pad;
+};
+
+// Working-column slot of a panel: slot index (-1: the wavefront's short slot) and the
+// column whose publication frees the slot (-1: none).
+struct SlotRef {
+    int32_t slot, wait;
 };
 
 // Everything pf_analyze derives from the pattern, on the host.
@@ -37,6 +63,11 @@ struct HostPlan {
     std::vector<int32_t> col_diag;                // N, relative position of the diagonal
     std::vector<int32_t> row_idx;                 // nnz_lu
     std::vector<JacDesc> desc;                    // nnz_lu Jacobian descriptors
+    // per Ybus entry (i, k): LU positions of dP_i/dangle_k, dP_i/d|V_k|, dQ_i/dangle_k,
+    // dQ_i/d|V_k| (-1 where the equation or unknown does not exist); per LU position: 1 if
+    // it holds a Jacobian entry, 0 for fill
+    std::vector<JPos> jpos;
+    std::vector<uint8_t> isj;
     // refactorization updates, per column j in ascending k
     std::vector<int32_t> upd_ptr;                 // N+1
     std::vector<Update> upd;
@@ -53,6 +84,17 @@ struct HostPlan {
     // processing orders of the panels: by refactorization level (a topological order of
     // the column DAG) and by back-substitution level (topological for the row DAG)
     std::vector<int32_t> lu_seq, bs_seq;
+    // working-column slots of the refactorization: a panel of at most slot_rows rows uses
+    // its wavefront's own slot; a longer panel uses one of n_long shared slots.  For each
+    // of the two panel orders (level, elimination) and each panel: {slot, column to wait
+    // for}: the r-th long panel of an order takes slot r mod n_long once the (r - n_long)-th
+    // has published, so slots are handed out in topological order; {-1, -1} for short
+    // panels.
+    int slot_rows = 0, n_long = 0;
+    std::vector<int32_t> lslot;                   // [2][n_panels][2]
+    // per order (0: level, 1: elimination) and position in that order
+    std::vector<LuPanel> lu_desc;                 // [2][n_panels]
+    std::vector<BsPanel> bs_desc;                 // [2][n_panels]
     // right-hand side and update maps
     std::vector<int32_t> bus_peq, bus_qeq;        // bus -> position of its P / Q equation, -1
     std::vector<int32_t> pos_upd;                 // position j -> bus * 2 + (unknown is |V|)
@@ -66,14 +108,17 @@ struct DevPlan {
     const int32_t *yrp, *yci, *yrow;
     const int8_t *bus_type;
     const int32_t *col_ptr, *col_diag;
-    const JacDesc *desc;
+    const JPos *jpos;
+    const uint8_t *isj;
     const int32_t *upd_ptr, *rel;
     const Update *upd;
     const int32_t *lev_ptr, *lev_cols, *bs_lev_ptr, *bs_lev_rows;
     const int32_t *bs_ptr, *bs_pos, *bs_col;
     const int32_t *bus_peq, *bus_qeq, *pos_upd;
     const int32_t *panel_ptr, *lu_seq, *bs_seq;
-    int n_panels;
+    const LuPanel *lu_desc;
+    const BsPanel *bs_desc;
+    int n_panels, slot_rows, n_long;
 };
 
 struct Plan {

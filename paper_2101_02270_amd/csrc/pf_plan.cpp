@@ -239,6 +239,16 @@ int analyze(int n, int nnzy, const int32_t *row_ptr, const int32_t *col_idx,
         }
     }
 
+    h.jpos.assign(h.nnzy, JPos{-1, -1, -1, -1});
+    h.isj.assign(nnzlu, 0);
+    for (int e = 0; e < nnzlu; e++) {
+        const JacDesc &d = h.desc[e];
+        if (d.p < 0) continue;
+        h.isj[e] = 1;
+        int32_t *slots = &h.jpos[d.p].pt;
+        slots[d.kind] = e;
+    }
+
     // ---- left-looking update lists with relative targets
     std::vector<int> where(N, -1);
     h.upd_ptr.assign(N + 1, 0);
@@ -342,6 +352,58 @@ int analyze(int n, int nnzy, const int32_t *row_ptr, const int32_t *col_idx,
         std::stable_sort(h.bs_seq.begin(), h.bs_seq.end(), [&](int a, int b) {
             return bk[a] != bk[b] ? bk[a] < bk[b] : a > b;
         });
+
+        // short working columns cover all but the longest ~4% of panels (at least 16 rows,
+        // a multiple of 8); the rest share two long slots
+        std::vector<int> rows(np);
+        for (int q = 0; q < np; q++) rows[q] = h.col_ptr[h.panel_ptr[q] + 1] - h.col_ptr[h.panel_ptr[q]];
+        std::vector<int> sorted_rows(rows);
+        std::sort(sorted_rows.begin(), sorted_rows.end());
+        const int p96 = np ? sorted_rows[std::min(np - 1, (int)(0.96 * np))] : 0;
+        h.slot_rows = std::max(16, (p96 + 7) / 8 * 8);
+        if (h.slot_rows >= h.max_col) { h.slot_rows = h.max_col; h.n_long = 0; }
+        else h.n_long = 2;
+        h.lslot.assign((size_t)4 * np, -1);
+        for (int order = 0; order < 2; order++) {
+            std::vector<int> long_cols;            // first column of each long panel in this order
+            for (int q = 0; q < np; q++) {
+                const int pi = order == 0 ? h.lu_seq[q] : q;
+                if (rows[pi] <= h.slot_rows) continue;
+                const int r = (int)long_cols.size();
+                int32_t *e = &h.lslot[((size_t)order * np + pi) * 2];
+                e[0] = r % h.n_long;
+                e[1] = r >= h.n_long ? long_cols[r - h.n_long] : -1;
+                long_cols.push_back(h.panel_ptr[pi]);
+            }
+        }
+    }
+
+    // ---- per-position panel descriptors of both orders
+    {
+        const int np = (int)h.panel_ptr.size() - 1;
+        h.lu_desc.resize((size_t)2 * np);
+        h.bs_desc.resize((size_t)2 * np);
+        for (int order = 0; order < 2; order++)
+            for (int q = 0; q < np; q++) {
+                {
+                    const int pi = order == 0 ? h.lu_seq[q] : q;
+                    const int j = h.panel_ptr[pi];
+                    const int two = h.panel_ptr[pi + 1] - j == 2;
+                    const int32_t *ls = &h.lslot[((size_t)order * np + pi) * 2];
+                    h.lu_desc[(size_t)order * np + q] =
+                        LuPanel{j | (two << 30), h.col_ptr[j], h.col_ptr[j + 1] - h.col_ptr[j], h.col_diag[j],
+                                h.upd_ptr[j], h.upd_ptr[j + 1], ls[0], ls[1]};
+                }
+                {
+                    const int pi = order == 0 ? h.bs_seq[q] : np - 1 - q;
+                    const int j = h.panel_ptr[pi];
+                    const int two = h.panel_ptr[pi + 1] - j == 2;
+                    const int jl = two ? j + 1 : j;
+                    h.bs_desc[(size_t)order * np + q] =
+                        BsPanel{j | (two << 30), h.col_ptr[j], two ? h.col_ptr[j + 1] : h.col_ptr[j], h.col_diag[j],
+                                h.bs_ptr[jl], h.bs_ptr[jl + 1], 0, 0};
+                }
+            }
     }
 
     // ---- right-hand side and update maps
@@ -356,6 +418,7 @@ int analyze(int n, int nnzy, const int32_t *row_ptr, const int32_t *col_idx,
         int uu = h.perm[j];
         h.pos_upd[j] = h.ubus[uu] * 2 + (uu >= h.npvpq ? 1 : 0);
     }
+    for (BsPanel &d : h.bs_desc) d.pu = h.pos_upd[d.j2 & ((1 << 30) - 1)];
     return PF_OK;
 }
 

@@ -46,7 +46,6 @@ void set_error(const std::string &msg) { g_err = msg; }
 
 enum Mode { MODE_SOLVE = 0, MODE_MISMATCH = 1, MODE_FACTOR = 2, MODE_STEP = 3 };
 
-constexpr int BUILD_CHUNK = 2;   // Jacobian entries per lane whose loads are issued together
 constexpr int UPD_GROUP = 4;     // column updates whose operand loads are issued together
 
 struct KArgs {
@@ -68,50 +67,55 @@ struct KArgs {
     unsigned long long *done_ticks;        // per-instance completion tick (may be null)
     const unsigned long long *t0;          // start tick the completion ticks are relative to
     int sched;                  // 0: level order, 1: elimination order
-    int tsz;                    // instances per tile (the body's T), read by the queue kernel
 };
+
+// sin and cos of a voltage angle.  Reduction x = k pi/2 + r with k = rint(2x/pi) and
+// pi/2 split into three doubles (c1 = RN(pi/2), c2 = RN(pi/2 - c1), c3 = RN(pi/2 - c1 - c2)),
+// each step one fused multiply-add; then the Taylor series of sin r (to r^17) and cos r (to
+// r^18) on |r| <= pi/4, whose truncation error is below 1e-19, and the quadrant k mod 4.
+// Absolute error a few ulp for |x| < 2^20 pi/2; larger angles (only seen in diverging
+// solves) keep a finite but less accurate result, and NaN propagates.  A short path with
+// few live registers: the general library routine carries a long-argument reduction.
+__device__ __forceinline__ void sincos_angle(double x, double *sn, double *cs)
+{
+    constexpr double two_over_pi = 0x1.45f306dc9c883p-1;
+    constexpr double c1 = 0x1.921fb54442d18p+0, c2 = 0x1.1a62633145c07p-54, c3 = -0x1.f1976b7ed8fbcp-110;
+    const double k = rint(x * two_over_pi);
+    double r = fma(-k, c1, x);
+    r = fma(-k, c2, r);
+    r = fma(-k, c3, r);
+    const double r2 = r * r;
+    // (-1)^m / (2m+1)!  and  (-1)^m / (2m)!
+    double ps = 2.8114572543455206e-15;
+    ps = fma(ps, r2, -7.647163731819816e-13);
+    ps = fma(ps, r2, 1.6059043836821613e-10);
+    ps = fma(ps, r2, -2.505210838544172e-08);
+    ps = fma(ps, r2, 2.7557319223985893e-06);
+    ps = fma(ps, r2, -0.0001984126984126984);
+    ps = fma(ps, r2, 0.008333333333333333);
+    ps = fma(ps, r2, -0.16666666666666666);
+    const double s = fma(r * r2, ps, r);
+    double pc = -1.5619206968586225e-16;
+    pc = fma(pc, r2, 4.779477332387385e-14);
+    pc = fma(pc, r2, -1.1470745597729725e-11);
+    pc = fma(pc, r2, 2.08767569878681e-09);
+    pc = fma(pc, r2, -2.755731922398589e-07);
+    pc = fma(pc, r2, 2.48015873015873e-05);
+    pc = fma(pc, r2, -0.001388888888888889);
+    pc = fma(pc, r2, 0.041666666666666664);
+    pc = fma(pc, r2, -0.5);
+    const double c = fma(r2, pc, 1.0);
+    const int q = (int)((long long)fmin(fmax(k, -0x1p52), 0x1p52) & 3);
+    const double s_out = (q & 1) ? c : s, c_out = (q & 1) ? s : c;
+    *sn = (q & 2) ? -s_out : s_out;
+    *cs = ((q + 1) & 2) ? -c_out : c_out;
+}
 
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// One Jacobian entry dF_e/dx_u from its descriptor (Sec. 3.1.2).  With w = V_i conj(Y_ik V_k):
-//   off-diagonal  dS_i/dangle_k = -j w,          dS_i/d|V_k| = w / |V_k|
-//   diagonal      dS_i/dangle_i = j (S_i - |V_i|^2 conj Y_ii),
-//                 dS_i/d|V_i|   = S_i / |V_i| + |V_i| conj Y_ii
-// P equations take the real part, Q equations the imaginary part.
-// The column's own bus k supplies V_k, |V_k| and I_k (loaded once per panel); each
-// off-diagonal entry needs only V_i and Y_ik (loaded by the caller).  The angle and |V| columns of a PQ bus share
-// the entry's Ybus element and row, so one call yields both derivatives:
-//   angle:  off-diagonal -j w, diagonal j (S_k - |V_k|^2 conj Y_kk)
-//   |V|:    off-diagonal w / |V_k|, diagonal S_k / |V_k| + |V_k| conj Y_kk
-// with w = V_i conj(Y_ik V_k); P rows take the real part, Q rows the imaginary part.
-struct JacPair {
-    double th, vm;
-};
-
-__device__ __forceinline__ JacPair jac_entry(const JacDesc d, double2 y, double2 v, double2 vk, double vmk,
-                                             double2 ik)
-{
-    if (d.p < 0) return JacPair{0.0, 0.0};
-    double tr, ti, vr, vi;     // d/d angle and d/d|V| of S_i, complex
-    if (d.i != d.k) {
-        const double cr = y.x * vk.x - y.y * vk.y, ci = y.x * vk.y + y.y * vk.x;     // Y_ik V_k
-        const double wr = v.x * cr + v.y * ci, wi = v.y * cr - v.x * ci;              // V_i conj(.)
-        tr = wi; ti = -wr;
-        const double inv = 1.0 / vmk;
-        vr = wr * inv; vi = wi * inv;
-    } else {
-        const double sr = vk.x * ik.x + vk.y * ik.y, si = vk.y * ik.x - vk.x * ik.y;  // S_k
-        const double m2 = vmk * vmk;
-        tr = -si - m2 * y.y; ti = sr - m2 * y.x;
-        vr = sr / vmk + vmk * y.x; vi = si / vmk - vmk * y.y;
-    }
-    const bool q = d.kind & 2;
-    return JacPair{q ? ti : tr, q ? vi : vr};
 }
 
 // Publication flags of the dataflow phases: one LDS byte per column (row).  A producer
@@ -200,15 +204,16 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     const size_t nT = (size_t)n * T;
     double *Vm = vec, *Va = vec + nT, *Ps = vec + 2 * nT, *Qs = vec + 3 * nT;
     double2 *Vc = reinterpret_cast<double2 *>(vec + 4 * nT);     // V = |V| e^{j angle}
-    double2 *Ic = reinterpret_cast<double2 *>(vec + 6 * nT);     // I = Y V
 
-    // per wavefront: two working columns (a panel) and two right-hand-side slots
-    R *xw = reinterpret_cast<R *>(smem_raw) + (size_t)wave * 2 * (P.max_col * T + T);
-    R *xw1 = xw + (size_t)P.max_col * T;
-    R *ysl = xw1 + (size_t)P.max_col * T;
+    // LDS: per wavefront a short working-column pair (slot_rows rows each), n_long shared
+    // long pairs (max_col rows each), per wavefront two right-hand-side slots, then one
+    // publication byte per column
+    R *const short_base = reinterpret_cast<R *>(smem_raw);
+    R *const long_base = short_base + (size_t)NW * 2 * P.slot_rows * T;
+    R *ysl = long_base + (size_t)P.n_long * 2 * P.max_col * T + (size_t)wave * 2 * T;
     R *ysl1 = ysl + T;
     unsigned char *done = reinterpret_cast<unsigned char *>(
-        reinterpret_cast<R *>(smem_raw) + (size_t)NW * 2 * (P.max_col * T + T));
+        long_base + (size_t)P.n_long * 2 * P.max_col * T + (size_t)NW * 2 * T);
     int *err = &s_err;
 
     // ---- boundary layout [B][n][2] -> tile layout [n][T]
@@ -235,32 +240,62 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         for (int i = slot; i < n; i += SLOTS) {
             double sn, cs;
             const double vm = Vm[i * T + t];
-            sincos(Va[i * T + t], &sn, &cs);
+            sincos_angle(Va[i * T + t], &sn, &cs);
             Vc[i * T + t] = make_double2(vm * cs, vm * sn);
         }
         __syncthreads();
+        // I = Y V, S = V conj(I) and F per bus; the same pass over the Ybus row writes the
+        // Jacobian entries of the row's equations into the LU array (Sec. 3.1.2): with
+        // w = V_i conj(Y_ik V_k), off-diagonal dS_i/dangle_k = -j w, dS_i/d|V_k| = w / |V_k|;
+        // diagonal dS_i/dangle_i = j (S_i - |V_i|^2 conj Y_ii), dS_i/d|V_i| = S_i / |V_i| +
+        // |V_i| conj Y_ii.  P rows take the real part, Q rows the imaginary part.
+        const bool build = a.mode != MODE_MISMATCH;
         double mx = 0.0;
         int bad = 0;
         for (int i = slot; i < n; i += SLOTS) {
-            double ir = 0.0, ii = 0.0;
-            for (int q = P.yrp[i]; q < P.yrp[i + 1]; q++) {
-                const double2 y = reinterpret_cast<const double2 *>(a.ybus)[q];
-                const double2 v = Vc[P.yci[q] * T + t];
-                ir += y.x * v.x - y.y * v.y;
-                ii += y.x * v.y + y.y * v.x;
-            }
-            Ic[i * T + t] = make_double2(ir, ii);
             const double2 vv = Vc[i * T + t];
-            const double vr = vv.x, vi = vv.y;
+            double ir = 0.0, ii = 0.0;
+            double2 ydg = make_double2(0.0, 0.0);
+            int qdg = -1;
+            for (int q = P.yrp[i]; q < P.yrp[i + 1]; q++) {
+                const int k = P.yci[q];
+                const double2 y = reinterpret_cast<const double2 *>(a.ybus)[q];
+                const double2 v = Vc[k * T + t];
+                const double cr = y.x * v.x - y.y * v.y, ci = y.x * v.y + y.y * v.x;     // Y_ik V_k
+                ir += cr;
+                ii += ci;
+                if (k == i) {
+                    ydg = y;
+                    qdg = q;
+                } else if (build) {
+                    const JPos jp = P.jpos[q];
+                    const double inv = 1.0 / Vm[k * T + t];
+                    const double wr = vv.x * cr + vv.y * ci, wi = vv.y * cr - vv.x * ci;
+                    if (jp.pt >= 0) LU[(size_t)jp.pt * T + t] = (R)wi;
+                    if (jp.pv >= 0) LU[(size_t)jp.pv * T + t] = (R)(wr * inv);
+                    if (jp.qt >= 0) LU[(size_t)jp.qt * T + t] = (R)(-wr);
+                    if (jp.qv >= 0) LU[(size_t)jp.qv * T + t] = (R)(wi * inv);
+                }
+            }
+            const double sr = vv.x * ir + vv.y * ii, si = vv.y * ir - vv.x * ii;       // S_i
+            if (build && qdg >= 0) {
+                const JPos jp = P.jpos[qdg];
+                const double vmi = Vm[i * T + t];
+                const double m2 = vmi * vmi;
+                if (jp.pt >= 0) LU[(size_t)jp.pt * T + t] = (R)(-si - m2 * ydg.y);
+                if (jp.pv >= 0) LU[(size_t)jp.pv * T + t] = (R)(sr / vmi + vmi * ydg.x);
+                if (jp.qt >= 0) LU[(size_t)jp.qt * T + t] = (R)(sr - m2 * ydg.x);
+                if (jp.qv >= 0) LU[(size_t)jp.qv * T + t] = (R)(si / vmi - vmi * ydg.y);
+            }
             const int pe = P.bus_peq[i], qe = P.bus_qeq[i];
             if (pe >= 0) {
-                const double f = (vr * ir + vi * ii) - Ps[i * T + t];
+                const double f = sr - Ps[i * T + t];
                 Yv[pe * T + t] = (R)f;
                 if (!isfinite(f)) bad = 1; else mx = fmax(mx, fabs(f));
                 if (a.mode == MODE_MISMATCH && valid) a.aux_out[(size_t)b * N + a.perm[pe]] = f;
             }
             if (qe >= 0) {
-                const double f = (vi * ir - vr * ii) - Qs[i * T + t];
+                const double f = si - Qs[i * T + t];
                 Yv[qe * T + t] = (R)f;
                 if (!isfinite(f)) bad = 1; else mx = fmax(mx, fabs(f));
                 if (a.mode == MODE_MISMATCH && valid) a.aux_out[(size_t)b * N + a.perm[qe]] = f;
@@ -311,40 +346,33 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         // earliest unfinished panel always has every source published and some wavefront
         // always makes progress; level order keeps independent panels side by side.
         for (int q = wave; q < P.n_panels; q += NW) {
-            const int pi = a.sched ? q : P.lu_seq[q];
-            const int j = P.panel_ptr[pi];
-            const bool two = P.panel_ptr[pi + 1] - j == 2;
-            const int cs = P.col_ptr[j];
-            const int cnt = P.col_ptr[j + 1] - cs;
-            const int dr = P.col_diag[j];
+            const LuPanel pd = P.lu_desc[(size_t)a.sched * P.n_panels + q];
+            const int j = pd.j2 & ((1 << 30) - 1);
+            const bool two = (pd.j2 >> 30) & 1;
+            const int cs = pd.cs, cnt = pd.cnt, dr = pd.dr;
+            R *xw, *xw1;
             {
-                const int kb = P.pos_upd[j] >> 1;      // bus of the panel's unknowns
-                const double2 vk = Vc[kb * T + t], ik = Ic[kb * T + t];
-                const double vmk = Vm[kb * T + t];
-                // descriptors of this lane's entries first, then every operand load, so that
-                // the loads of several entries are in flight together
-                for (int e0 = s; e0 < cnt; e0 += BUILD_CHUNK * SL) {
-                    JacDesc dd[BUILD_CHUNK];
-#pragma unroll
-                    for (int q = 0; q < BUILD_CHUNK; q++) {
-                        const int e = e0 + q * SL;
-                        dd[q] = e < cnt ? P.desc[cs + e] : JacDesc{-1, 0, 0, 0};
-                    }
-                    double2 yy[BUILD_CHUNK], vv[BUILD_CHUNK];
-#pragma unroll
-                    for (int q = 0; q < BUILD_CHUNK; q++) {
-                        yy[q] = dd[q].p >= 0 ? reinterpret_cast<const double2 *>(a.ybus)[dd[q].p] : make_double2(0.0, 0.0);
-                        vv[q] = (dd[q].p >= 0 && dd[q].i != dd[q].k) ? Vc[dd[q].i * T + t] : vk;
-                    }
-#pragma unroll
-                    for (int q = 0; q < BUILD_CHUNK; q++) {
-                        const int e = e0 + q * SL;
-                        if (e < cnt) {
-                            const JacPair jp = jac_entry(dd[q], yy[q], vv[q], vk, vmk, ik);
-                            xw[e * T + t] = (R)((dd[q].kind & 1) ? jp.vm : jp.th);
-                            if (two) xw1[e * T + t] = (R)jp.vm;
-                        }
-                    }
+                const SlotRef ls{pd.slot, pd.wait};
+                if (ls.slot < 0) {
+                    xw = short_base + (size_t)wave * 2 * P.slot_rows * T;
+                    xw1 = xw + (size_t)P.slot_rows * T;
+                } else {
+                    // a long panel: its shared slot is free once the panel that used it
+                    // before (earlier in the same topological order) has published
+                    if (ls.wait >= 0) wait_published(done, ls.wait, err);
+                    xw = long_base + (size_t)ls.slot * 2 * P.max_col * T;
+                    xw1 = xw + (size_t)P.max_col * T;
+                }
+            }
+            // the panel's Jacobian values (written by the mismatch pass; fill positions read
+            // as zero): both columns of a pair share the row list and the fill pattern
+            for (int e = s; e < cnt; e += SL) {
+                const bool f = P.isj[cs + e];
+                const R v0 = LU[(size_t)(cs + e) * T + t];
+                xw[e * T + t] = f ? v0 : (R)0;
+                if (two) {
+                    const R v1 = LU[(size_t)(cs + cnt + e) * T + t];
+                    xw1[e * T + t] = f ? v1 : (R)0;
                 }
             }
             if (s == 0) {
@@ -355,7 +383,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             // the run of following updates whose sources are already published (up to
             // UPD_GROUP) has its operand loads issued together, then the updates are applied
             // one after another in LDS (the order of the arithmetic is unchanged).
-            const int u0 = P.upd_ptr[j], u1 = P.upd_ptr[j + 1];
+            const int u0 = pd.u0, u1 = pd.u1;
             for (int ub = u0; ub < u1;) {
                 Update ups[UPD_GROUP];
                 ups[0] = P.upd[ub];
@@ -462,12 +490,23 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         // column set i > j+1, and U(j, i), U(j+1, i) sit next to each other in column i.
         const bool upd_v = (a.mode == MODE_SOLVE);
         for (int q = wave; q < P.n_panels; q += NW) {
-            const int pi = a.sched ? P.n_panels - 1 - q : P.bs_seq[q];
-            const int j = P.panel_ptr[pi];
-            const bool two = P.panel_ptr[pi + 1] - j == 2;
-            const int jl = two ? j + 1 : j;            // the panel's last row
+            const BsPanel pd = P.bs_desc[(size_t)a.sched * P.n_panels + q];
+            const int j = pd.j2 & ((1 << 30) - 1);
+            const bool two = (pd.j2 >> 30) & 1;
+            const int cs = pd.cs, dr = pd.dr, cs1 = pd.cs1;
+            const int pu = pd.pu;
+            const int bus = pu >> 1;
+            // operands that no other row changes, loaded before the wait so that their
+            // latency overlaps it: right-hand sides, diagonal (and for a pair the coupling
+            // U(j, j+1)), and the voltages to update
+            const R y0 = Yv[j * T + t];
+            const R d0 = LU[(size_t)(cs + dr) * T + t];
+            const R y1 = two ? Yv[(j + 1) * T + t] : (R)0;
+            const R d1 = two ? LU[(size_t)(cs1 + dr + 1) * T + t] : (R)1;
+            const R u01 = two ? LU[(size_t)(cs1 + dr) * T + t] : (R)0;
+            const double vm_old = Vm[bus * T + t], va_old = Va[bus * T + t];
             R acc0 = 0, acc1 = 0;
-            const int q0 = P.bs_ptr[jl], q1 = P.bs_ptr[jl + 1];
+            const int q0 = pd.q0, q1 = pd.q1;
             wait_all_published(done, P.bs_col, q0, q1, lane, err);
             for (int q = q0 + s; q < q1; q += SL) {
                 const R z = Yv[P.bs_col[q] * T + t];
@@ -485,22 +524,23 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 acc1 += __shfl_xor(acc1, off);
             }
             if (s == 0) {
-                const int cs = P.col_ptr[j], dr = P.col_diag[j];
                 R zl = 0;
                 if (two) {
-                    const int cs1 = P.col_ptr[j + 1];
-                    zl = (Yv[(j + 1) * T + t] - acc1) / LU[(size_t)(cs1 + dr + 1) * T + t];
+                    zl = (y1 - acc1) / d1;
                     Yv[(j + 1) * T + t] = zl;
-                    acc0 = fma(LU[(size_t)(cs1 + dr) * T + t], zl, acc0);
+                    acc0 = fma(u01, zl, acc0);
                 }
-                const R z0 = (Yv[j * T + t] - acc0) / LU[(size_t)(cs + dr) * T + t];
+                const R z0 = (y0 - acc0) / d0;
                 Yv[j * T + t] = z0;
                 if (upd_v && s_active[t]) {
-                    const int pu = P.pos_upd[j];
-                    const int bus = pu >> 1;
-                    if (pu & 1) Vm[bus * T + t] -= (double)z0;
-                    else Va[bus * T + t] -= (double)z0;
-                    if (two) Vm[bus * T + t] -= (double)zl;
+                    if (two) {
+                        Va[bus * T + t] = va_old - (double)z0;
+                        Vm[bus * T + t] = vm_old - (double)zl;
+                    } else if (pu & 1) {
+                        Vm[bus * T + t] = vm_old - (double)z0;
+                    } else {
+                        Va[bus * T + t] = va_old - (double)z0;
+                    }
                 }
             }
             wave_sync();
@@ -533,8 +573,10 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     }
 }
 
+// Four waves per SIMD: the refactorization is bound by dependent memory round trips, so
+// resident wavefronts matter more than the few registers spilled at this bound.
 template <typename R, int T, int NW>
-__global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void nr_tile_kernel(KArgs a)
 {
     nr_tile_body<R, T, NW>(a, blockIdx.x);
 }
@@ -542,12 +584,14 @@ __global__ __launch_bounds__(NW * 64) void nr_tile_kernel(KArgs a)
 // Persistent launch over a queue of work items (one per pattern / batch): workgroups pop
 // tiles from a global counter until every item's tiles are done.  prefix[i] is the first
 // tile of item i (prefix[nitems] = total); items are ordered by the caller.
-// Items may use different tile sizes: the body is selected per item (the workgroup size,
-// set by NW, is common to the launch).  Every wave leaves the loop once the counter has
-// passed the last tile, so the grid always drains.
-template <typename R, int NW>
-__global__ __launch_bounds__(NW * 64) void nr_queue_kernel(const KArgs *items, const int *prefix, int nitems,
-                                                           int *counter)
+// Persistent launch over a queue of work items (one per pattern / batch) that share one
+// precision, tile size and workgroup size: workgroups pop tiles from a global counter until
+// every item's tiles are done.  prefix[i] is the first tile of item i (prefix[nitems] =
+// total).  Every wave leaves the loop once the counter has passed the last tile, so the
+// grid always drains.
+template <typename R, int T, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void nr_queue_kernel(
+    const KArgs *items, const int *prefix, int nitems, int *counter)
 {
     __shared__ int s_tile;
     const int total = prefix[nitems];
@@ -559,18 +603,7 @@ __global__ __launch_bounds__(NW * 64) void nr_queue_kernel(const KArgs *items, c
         if (tg >= total) break;
         int it = 0;
         while (it + 1 < nitems && prefix[it + 1] <= tg) it++;
-        const KArgs &a = items[it];
-        const int tile = tg - prefix[it];
-        const int tsz = __builtin_amdgcn_readfirstlane(a.tsz);
-        if constexpr (sizeof(R) == 8) {
-            if (tsz == 4) nr_tile_body<R, 4, NW>(a, tile);
-            else if (tsz == 8) nr_tile_body<R, 8, NW>(a, tile);
-            else nr_tile_body<R, 16, NW>(a, tile);
-        } else {
-            if (tsz == 8) nr_tile_body<R, 8, NW>(a, tile);
-            else if (tsz == 16) nr_tile_body<R, 16, NW>(a, tile);
-            else nr_tile_body<R, 32, NW>(a, tile);
-        }
+        nr_tile_body<R, T, NW>(items[it], tg - prefix[it]);
     }
 }
 
@@ -599,14 +632,15 @@ static TileLayout tile_layout(const HostPlan &h, const Config &c)
     TileLayout L;
     L.off_y = align256((size_t)(h.col_ptr.empty() ? 0 : h.col_ptr[h.N]) * c.tile * rs);
     L.off_vec = L.off_y + align256((size_t)h.N * c.tile * rs);
-    L.bytes = L.off_vec + align256((size_t)8 * h.n * c.tile * 8);
+    L.bytes = L.off_vec + align256((size_t)6 * h.n * c.tile * 8);
     return L;
 }
 
 static size_t lds_bytes(const HostPlan &h, const Config &c)
 {
     const size_t rs = c.precision == PF_FP32_LU ? 4 : 8;
-    return (size_t)c.waves * 2 * ((size_t)h.max_col * c.tile + c.tile) * rs + (size_t)h.N;
+    return ((size_t)c.waves * 2 * ((size_t)h.slot_rows * c.tile + c.tile) + (size_t)h.n_long * 2 * h.max_col * c.tile) * rs +
+           (size_t)h.N;
 }
 
 static size_t lds_bytes(const HostPlan &h, const Config &c);
@@ -663,17 +697,25 @@ static hipError_t launch_t(const KArgs &a, int grid, size_t lds, hipStream_t st)
     default: return launch_t<R, T, 8>(a, grid, lds, st);                       \
     }
 
-// The persistent queue kernel for a precision and a workgroup size.
-static const void *queue_kernel(int precision, int waves)
+// The persistent queue kernel for a launch configuration.
+template <typename R, int T>
+static const void *queue_kernel_nw(int waves)
 {
-    if (precision == PF_FP64) {
-        if (waves == 2) return reinterpret_cast<const void *>(nr_queue_kernel<double, 2>);
-        if (waves == 4) return reinterpret_cast<const void *>(nr_queue_kernel<double, 4>);
-        return reinterpret_cast<const void *>(nr_queue_kernel<double, 8>);
+    if (waves == 2) return reinterpret_cast<const void *>(nr_queue_kernel<R, T, 2>);
+    if (waves == 4) return reinterpret_cast<const void *>(nr_queue_kernel<R, T, 4>);
+    return reinterpret_cast<const void *>(nr_queue_kernel<R, T, 8>);
+}
+
+static const void *queue_kernel(const Config &c)
+{
+    if (c.precision == PF_FP64) {
+        if (c.tile == 4) return queue_kernel_nw<double, 4>(c.waves);
+        if (c.tile == 8) return queue_kernel_nw<double, 8>(c.waves);
+        return queue_kernel_nw<double, 16>(c.waves);
     }
-    if (waves == 2) return reinterpret_cast<const void *>(nr_queue_kernel<float, 2>);
-    if (waves == 4) return reinterpret_cast<const void *>(nr_queue_kernel<float, 4>);
-    return reinterpret_cast<const void *>(nr_queue_kernel<float, 8>);
+    if (c.tile == 8) return queue_kernel_nw<float, 8>(c.waves);
+    if (c.tile == 16) return queue_kernel_nw<float, 16>(c.waves);
+    return queue_kernel_nw<float, 32>(c.waves);
 }
 
 static hipError_t launch(const Config &c, const KArgs &a, int grid, size_t lds, hipStream_t st)
@@ -734,7 +776,6 @@ static int make_args(Plan *pl, const Config &c, int32_t batch, const double *ybu
     a.ws = reinterpret_cast<char *>(workspace);
     a.tile_bytes = L.bytes; a.off_y = L.off_y; a.off_vec = L.off_vec;
     a.sched = c.schedule;
-    a.tsz = c.tile;
     a.v_out = v_out; a.iters_out = iters_out; a.conv_out = conv_out; a.status_out = status_out;
     a.aux_out = aux; a.aux2_out = aux2;
     return PF_OK;
@@ -782,24 +823,25 @@ static int upload(Plan *pl)
     DevOffsets off;
     const size_t o_yrp = off.add(h.yrp), o_yci = off.add(h.yci), o_yrow = off.add(h.yrow);
     const size_t o_bt = off.add(h.bus_type), o_cp = off.add(h.col_ptr), o_cd = off.add(h.col_diag);
-    const size_t o_desc = off.add(h.desc), o_up = off.add(h.upd_ptr), o_rel = off.add(h.rel);
+    const size_t o_jpos = off.add(h.jpos), o_isj = off.add(h.isj), o_up = off.add(h.upd_ptr), o_rel = off.add(h.rel);
     const size_t o_upd = off.add(h.upd), o_lp = off.add(h.lev_ptr);
     const size_t o_lc = off.add(h.lev_cols), o_blp = off.add(h.bs_lev_ptr), o_blr = off.add(h.bs_lev_rows);
     const size_t o_bp = off.add(h.bs_ptr), o_bpos = off.add(h.bs_pos), o_bcol = off.add(h.bs_col);
     const size_t o_pe = off.add(h.bus_peq), o_qe = off.add(h.bus_qeq), o_pu = off.add(h.pos_upd);
     const size_t o_perm = off.add(h.perm), o_pp = off.add(h.panel_ptr);
     const size_t o_ls = off.add(h.lu_seq), o_bsq = off.add(h.bs_seq);
+    const size_t o_lud = off.add(h.lu_desc), o_bsd = off.add(h.bs_desc);
     std::vector<char> host(off.bytes, 0);
     auto put = [&](size_t o, const auto &v) {
         if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * sizeof(v[0]));
     };
     put(o_yrp, h.yrp); put(o_yci, h.yci); put(o_yrow, h.yrow); put(o_bt, h.bus_type);
-    put(o_cp, h.col_ptr); put(o_cd, h.col_diag); put(o_desc, h.desc); put(o_up, h.upd_ptr);
+    put(o_cp, h.col_ptr); put(o_cd, h.col_diag); put(o_jpos, h.jpos); put(o_isj, h.isj); put(o_up, h.upd_ptr);
     put(o_rel, h.rel); put(o_upd, h.upd); put(o_lp, h.lev_ptr);
     put(o_lc, h.lev_cols); put(o_blp, h.bs_lev_ptr); put(o_blr, h.bs_lev_rows); put(o_bp, h.bs_ptr);
     put(o_bpos, h.bs_pos); put(o_bcol, h.bs_col); put(o_pe, h.bus_peq); put(o_qe, h.bus_qeq);
     put(o_pu, h.pos_upd); put(o_perm, h.perm); put(o_pp, h.panel_ptr);
-    put(o_ls, h.lu_seq); put(o_bsq, h.bs_seq);
+    put(o_ls, h.lu_seq); put(o_bsq, h.bs_seq); put(o_lud, h.lu_desc); put(o_bsd, h.bs_desc);
     void *dm = nullptr;
     if (hipMalloc(&dm, off.bytes) != hipSuccess) { set_error("hipMalloc of the plan failed"); return PF_ENOMEM; }
     if (hipMemcpy(dm, host.data(), off.bytes, hipMemcpyHostToDevice) != hipSuccess) {
@@ -816,7 +858,7 @@ static int upload(Plan *pl)
     d.max_col = h.max_col; d.npvpq = h.npvpq;
     d.yrp = (const int32_t *)(D + o_yrp); d.yci = (const int32_t *)(D + o_yci); d.yrow = (const int32_t *)(D + o_yrow);
     d.bus_type = (const int8_t *)(D + o_bt);
-    d.col_ptr = (const int32_t *)(D + o_cp); d.col_diag = (const int32_t *)(D + o_cd); d.desc = (const JacDesc *)(D + o_desc);
+    d.col_ptr = (const int32_t *)(D + o_cp); d.col_diag = (const int32_t *)(D + o_cd); d.jpos = (const JPos *)(D + o_jpos); d.isj = (const uint8_t *)(D + o_isj);
     d.upd_ptr = (const int32_t *)(D + o_up); d.rel = (const int32_t *)(D + o_rel);
     d.upd = (const Update *)(D + o_upd);
     d.lev_ptr = (const int32_t *)(D + o_lp); d.lev_cols = (const int32_t *)(D + o_lc);
@@ -827,7 +869,11 @@ static int upload(Plan *pl)
     d.panel_ptr = (const int32_t *)(D + o_pp);
     d.lu_seq = (const int32_t *)(D + o_ls);
     d.bs_seq = (const int32_t *)(D + o_bsq);
+    d.lu_desc = (const LuPanel *)(D + o_lud);
+    d.bs_desc = (const BsPanel *)(D + o_bsd);
     d.n_panels = (int)h.panel_ptr.size() - 1;
+    d.slot_rows = h.slot_rows;
+    d.n_long = h.n_long;
     return PF_OK;
 }
 
@@ -908,10 +954,13 @@ static double tile_cost(const QueueItem &it)
 static int queue_build(Queue *q)
 {
     queue_release(q);
-    // groups keyed by (precision, waves), items ordered by cost per tile
-    std::map<std::pair<int, int>, std::vector<int>> groups;
+    // groups keyed by (precision, tile, waves), items ordered by cost per tile
+    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
     for (int i = 0; i < (int)q->items.size(); i++)
-        if (q->items[i].batch > 0) groups[{q->items[i].c.precision, q->items[i].c.waves}].push_back(i);
+        if (q->items[i].batch > 0) {
+            const Config &c = q->items[i].c;
+            groups[std::make_tuple(c.precision, c.tile, c.waves)].push_back(i);
+        }
     for (auto &g : groups)
         std::stable_sort(g.second.begin(), g.second.end(),
                          [&](int x, int y) { return tile_cost(q->items[x]) > tile_cost(q->items[y]); });
@@ -955,8 +1004,8 @@ static int queue_build(Queue *q)
     int pos = 0, pre = 0;
     q->n_tiles = 0; q->n_instances = 0;
     for (auto &g : groups) {
-        GroupLaunch L{queue_kernel(g.first.first, g.first.second), pos, (int)g.second.size(), pre,
-                      g.first.second, 0};
+        const Config &gc = q->items[g.second[0]].c;
+        GroupLaunch L{queue_kernel(gc), pos, (int)g.second.size(), pre, gc.waves, 0};
         int acc = 0;
         for (int i : g.second) {
             const QueueItem &it = q->items[i];
@@ -1278,7 +1327,7 @@ int pf_queue_info(pf_queue queue, pf_queue_info_t *o)
     o->n_items = (int32_t)q->items.size();
     o->built = q->built ? 1 : 0;
     o->n_groups = (int32_t)q->grid.size();
-    for (int i = 0; i < (int)q->grid.size() && i < 6; i++) o->grid[i] = q->grid[i];
+    for (int i = 0; i < (int)q->grid.size() && i < 18; i++) o->grid[i] = q->grid[i];
     o->n_tiles = q->n_tiles;
     o->n_instances = q->n_instances;
     o->workspace_bytes = q->ws_bytes;
