@@ -144,6 +144,21 @@ int pf_solve_batch(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus
  *   pf_eval_step:     dx_out [device] [batch][N] solution of J(V) dx = F(V) in unknown
  *                     order (so that V_new = V - dx).
  */
+/*
+ * pf_solve_batch_warm: pf_solve_batch from the start v0 (e.g. a learned prediction) with
+ * an in-kernel fallback: an instance whose attempt from v0 fails (non-finite mismatch, an
+ * update that does not reduce max|F|, max_iter updates without convergence, or a zero
+ * pivot) restarts once from v_fallback
+ * [device, B x n_bus x 2, same layout as v0; typically the flat start], with a fresh
+ * max_iter budget.  iters_out counts the voltage updates of both attempts; status and
+ * converged describe the final attempt.  Other arguments and errors as pf_solve_batch.
+ */
+int pf_solve_batch_warm(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus_batched,
+                        const double *sbus, const double *v0, const double *v_fallback, double tol,
+                        int32_t max_iter, const pf_solve_opts *opts, void *workspace,
+                        size_t workspace_bytes, double *v_out, int32_t *iters_out, uint8_t *converged_out,
+                        int8_t *status_out, void *stream);
+
 int pf_eval_mismatch(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
                      const double *v, const pf_solve_opts *opts, void *workspace,
                      size_t workspace_bytes, double *f_out, double *normf_out, void *stream);

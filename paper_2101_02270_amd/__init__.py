@@ -27,7 +27,7 @@ EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
             "pf_eval_step", "pf_plan_destroy", "pf_last_error", "pf_mlp_gemm",
             "pf_mlp_act_backward", "pf_mlp_mse", "pf_mlp_adam", "pf_mlp_to_bf16",
             "pf_mlp_features", "pf_mlp_warm_v0", "pf_queue_create", "pf_queue_add",
-            "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune"]
+            "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune", "pf_solve_batch_warm"]
 
 
 class PfError(RuntimeError):
@@ -95,6 +95,9 @@ def lib():
         L.pf_mlp_to_bf16.argtypes = [i64, _vp, _vp, _vp]
         L.pf_mlp_features.argtypes = [i32, i32, _vp, _vp, _vp, _vp, i32, _vp, _vp, _vp, _vp]
         L.pf_mlp_warm_v0.argtypes = [i32, i32, _vp, _vp, i32, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.pf_solve_batch_warm.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, _vp,
+                                          ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Opts), _vp,
+                                          ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
         L.pf_queue_create.argtypes = [ctypes.POINTER(_vp)]
         L.pf_queue_add.argtypes = [_vp, _vp, i32, _vp, _vp, _vp, ctypes.c_double, i32,
                                    ctypes.POINTER(_Opts), _vp, _vp, _vp, _vp, _vp]
@@ -238,9 +241,12 @@ def _as_pairs(x, name):
 
 def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
                 precision: int = PF_FP64, tile: int = 0, waves: int = 0, workspace=None,
-                stream=None, out: Optional[Result] = None, schedule: int = 0) -> Result:
+                stream=None, out: Optional[Result] = None, schedule: int = 0,
+                v_fallback=None) -> Result:
     """Run pf_solve_batch on device tensors: ybus complex128 [nnz_y], sbus complex128 [B][n],
-    v0 float64 [B][n][2].  Returns device tensors (valid once the stream synchronises)."""
+    v0 float64 [B][n][2].  With v_fallback (same shape as v0) pf_solve_batch_warm runs
+    instead: instances that fail from v0 restart once from v_fallback inside the kernel.
+    Returns device tensors (valid once the stream synchronises)."""
     torch = _torch()
     B = int(v0.shape[0])
     yp, _ = _ybus_view(plan, ybus)
@@ -254,11 +260,17 @@ def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 1
                      status=torch.empty(B, dtype=torch.int8, device=v0.device))
     opts = _Opts(precision, tile, waves, schedule)
     workspace, wp, avail = _workspace(plan, B, opts, workspace)
-    rc = lib().pf_solve_batch(plan._h, B, yp, 0, sp, vp, float(tol), int(max_iter), ctypes.byref(opts),
-                              wp, avail, _vp(out.v.data_ptr()), _vp(out.iters.data_ptr()),
-                              _vp(out.converged.data_ptr()), _vp(out.status.data_ptr()),
-                              _stream_ptr(stream))
-    _check(rc, "pf_solve_batch")
+    outs = (_vp(out.v.data_ptr()), _vp(out.iters.data_ptr()), _vp(out.converged.data_ptr()),
+            _vp(out.status.data_ptr()), _stream_ptr(stream))
+    if v_fallback is None:
+        rc = lib().pf_solve_batch(plan._h, B, yp, 0, sp, vp, float(tol), int(max_iter),
+                                  ctypes.byref(opts), wp, avail, *outs)
+        _check(rc, "pf_solve_batch")
+    else:
+        fp = _dev_ptr(v_fallback, torch.float64, (B, plan.n, 2), "v_fallback")
+        rc = lib().pf_solve_batch_warm(plan._h, B, yp, 0, sp, vp, fp, float(tol), int(max_iter),
+                                       ctypes.byref(opts), wp, avail, *outs)
+        _check(rc, "pf_solve_batch_warm")
     out._workspace = workspace
     return out
 

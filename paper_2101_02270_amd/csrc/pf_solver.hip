@@ -54,6 +54,7 @@ struct KArgs {
     const double *ybus;         // [nnzy][2]
     const double *sbus;         // [B][n][2]
     const double *v0;           // [B][n][2]
+    const double *v_fb;         // [B][n][2] restart point after a failed first attempt (may be null)
     double tol;
     int max_iter, batch, mode;
     char *ws;
@@ -143,30 +144,6 @@ __device__ __forceinline__ void wait_published(unsigned char *flags, int j, int 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Wait until every row bs_col[q], q0 <= q < q1, is published: the lanes poll their share of
-// the flags in parallel and the wavefront votes.  Bounded like wait_published.
-__device__ __forceinline__ void wait_all_published(unsigned char *flags, const int32_t *cols, int q0, int q1,
-                                                   int lane, int *err)
-{
-    for (int qb = q0; qb < q1; qb += 64) {
-        const int q = qb + lane;
-        const int c = q < q1 ? cols[q] : -1;
-        for (unsigned spins = 0;; ++spins) {
-            const bool ok = c < 0 || __hip_atomic_load(&flags[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (__all(ok)) break;
-            const int e = __builtin_amdgcn_readfirstlane(
-                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-            if (e) break;
-            if (spins >= (1u << 22)) {
-                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 // The whole Newton loop of one tile (T instances) by one workgroup.  Called by the
 // one-tile-per-workgroup kernel and by the persistent multi-pattern queue kernel.
 template <typename R, int T, int NW>
@@ -175,11 +152,14 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     constexpr int SL = 64 / T;          // sub-lanes per instance inside a wavefront
     constexpr int NT = NW * 64;
     constexpr int SLOTS = NT / T;       // bus slots per workgroup
+    constexpr int A_ROWS = 2;            // panel rows per lane whose loads are issued together
 
     extern __shared__ char smem_raw[];
     __shared__ double s_red[NW][T];
     __shared__ int s_bad[NW][T];
     __shared__ int s_active[T], s_status[T], s_iters[T], s_piv[T];
+    __shared__ int s_retry[T], s_reset[T], s_it0[T], s_nupd[T];
+    __shared__ double s_prevf[T];
     __shared__ double s_normf[T];
     __shared__ int s_any, s_err;
 
@@ -231,11 +211,24 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         s_active[t] = valid ? 1 : 0;
         s_status[t] = PF_ST_MAXITER;
         s_iters[t] = 0;
+        s_retry[t] = 0; s_reset[t] = 0; s_it0[t] = 0; s_nupd[t] = 0;
+        s_prevf[t] = INFINITY;
     }
     if (tid == 0) s_err = 0;
     __syncthreads();
 
     for (int it = 0;; ++it) {
+        // an instance whose first attempt failed restarts from the fallback point
+        if (a.v_fb) {
+            if (s_reset[t] && valid)
+                for (int i = slot; i < n; i += SLOTS) {
+                    const size_t o = ((size_t)b * n + i) * 2;
+                    Vm[i * T + t] = a.v_fb[o];
+                    Va[i * T + t] = a.v_fb[o + 1];
+                }
+            __syncthreads();
+            if (tid < T) s_reset[t] = 0;
+        }
         // ============================ M: mismatch and convergence test
         for (int i = slot; i < n; i += SLOTS) {
             double sn, cs;
@@ -316,9 +309,19 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             s_normf[t] = nb ? NAN : nf;
             s_piv[t] = 0;
             if (s_active[t] && a.mode == MODE_SOLVE) {
-                if (nb) { s_status[t] = PF_ST_NONFINITE; s_active[t] = 0; s_iters[t] = it; }
-                else if (nf < a.tol) { s_status[t] = PF_ST_CONVERGED; s_active[t] = 0; s_iters[t] = it; }
-                else if (it >= a.max_iter) { s_status[t] = PF_ST_MAXITER; s_active[t] = 0; s_iters[t] = it; }
+                // iters counts voltage updates over all attempts; max_iter bounds each attempt
+                int fail = 0;
+                if (nb) fail = PF_ST_NONFINITE;
+                else if (nf < a.tol) { s_status[t] = PF_ST_CONVERGED; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
+                else if (it - s_it0[t] >= a.max_iter) fail = PF_ST_MAXITER;
+                // an attempt that has a fallback gives up as soon as an update fails to
+                // reduce the mismatch (Newton from a good start contracts every step)
+                else if (a.v_fb && !s_retry[t] && !(nf < s_prevf[t])) fail = PF_ST_MAXITER;
+                s_prevf[t] = nf;
+                if (fail) {
+                    if (a.v_fb && !s_retry[t]) { s_retry[t] = 1; s_reset[t] = 1; s_it0[t] = it + 1; }
+                    else { s_status[t] = fail; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
+                }
             }
         }
         __syncthreads();
@@ -365,19 +368,40 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 }
             }
             // the panel's Jacobian values (written by the mismatch pass; fill positions read
-            // as zero): both columns of a pair share the row list and the fill pattern
-            for (int e = s; e < cnt; e += SL) {
-                const bool f = P.isj[cs + e];
-                const R v0 = LU[(size_t)(cs + e) * T + t];
-                xw[e * T + t] = f ? v0 : (R)0;
-                if (two) {
-                    const R v1 = LU[(size_t)(cs + cnt + e) * T + t];
-                    xw1[e * T + t] = f ? v1 : (R)0;
+            // as zero; both columns of a pair share the row list and the fill pattern) and
+            // right-hand sides.  Every load of the first A_ROWS rows per lane is issued before
+            // any is used, so they cost one memory round trip together.
+            {
+                R a0[A_ROWS], a1[A_ROWS];
+                unsigned char f[A_ROWS];
+#pragma unroll
+                for (int r = 0; r < A_ROWS; r++) {
+                    const int e = min(s + r * SL, cnt - 1);      // rows past the end re-read the last
+                    f[r] = P.isj[cs + e];
+                    a0[r] = LU[(size_t)(cs + e) * T + t];
+                    a1[r] = LU[(size_t)(cs + (two ? cnt : 0) + e) * T + t];
                 }
-            }
-            if (s == 0) {
-                ysl[t] = Yv[j * T + t];
-                if (two) ysl1[t] = Yv[(j + 1) * T + t];
+                const R y0 = Yv[j * T + t];
+                const R y1 = Yv[(j + (two ? 1 : 0)) * T + t];
+#pragma unroll
+                for (int r = 0; r < A_ROWS; r++) {
+                    const int e = s + r * SL;
+                    if (e < cnt) {
+                        xw[e * T + t] = f[r] ? a0[r] : (R)0;
+                        if (two) xw1[e * T + t] = f[r] ? a1[r] : (R)0;
+                    }
+                }
+                for (int e = s + A_ROWS * SL; e < cnt; e += SL) {
+                    const bool fe = P.isj[cs + e];
+                    const R v0 = LU[(size_t)(cs + e) * T + t];
+                    const R v1 = two ? LU[(size_t)(cs + cnt + e) * T + t] : (R)0;
+                    xw[e * T + t] = fe ? v0 : (R)0;
+                    if (two) xw1[e * T + t] = fe ? v1 : (R)0;
+                }
+                if (s == 0) {
+                    ysl[t] = y0;
+                    if (two) ysl1[t] = y1;
+                }
             }
             // Updates in ascending source order.  After waiting for the first pending source,
             // the run of following updates whose sources are already published (up to
@@ -472,8 +496,9 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             if (two) __hip_atomic_store(&done[j + 1], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         __syncthreads();
-        if (tid < T && s_piv[t] && s_active[t] && a.mode == MODE_SOLVE) {
-            s_status[t] = PF_ST_PIVOT; s_active[t] = 0; s_iters[t] = it;
+        if (tid < T && s_piv[t] && s_active[t] && !s_reset[t] && a.mode == MODE_SOLVE) {
+            if (a.v_fb && !s_retry[t]) { s_retry[t] = 1; s_reset[t] = 1; s_it0[t] = it + 1; }
+            else { s_status[t] = PF_ST_PIVOT; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
         }
         if (a.mode == MODE_FACTOR) {
             const size_t nnz = (size_t)P.nnzlu;
@@ -507,15 +532,37 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             const double vm_old = Vm[bus * T + t], va_old = Va[bus * T + t];
             R acc0 = 0, acc1 = 0;
             const int q0 = pd.q0, q1 = pd.q1;
-            wait_all_published(done, P.bs_col, q0, q1, lane, err);
-            for (int q = q0 + s; q < q1; q += SL) {
-                const R z = Yv[P.bs_col[q] * T + t];
-                const size_t pq = (size_t)P.bs_pos[q];
-                if (two) {
-                    acc1 = fma(LU[pq * T + t], z, acc1);
-                    acc0 = fma(LU[(pq - 1) * T + t], z, acc0);
-                } else {
-                    acc0 = fma(LU[pq * T + t], z, acc0);
+            // SL entries of the row at a time: each lane loads its entry's column and
+            // position, the wavefront waits until all those rows are published, then the
+            // operands are loaded
+            for (int qb = q0; qb < q1; qb += SL) {
+                const int q = qb + s;
+                const bool in = q < q1;
+                const int c = in ? P.bs_col[q] : -1;
+                const int pq = in ? P.bs_pos[q] : 1;
+                for (unsigned spins = 0;; ++spins) {
+                    const bool ok = c < 0 || __hip_atomic_load(&done[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (__all(ok)) break;
+                    const int e = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                    if (e) break;
+                    if (spins >= (1u << 22)) {
+                        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const R z = Yv[(in ? c : j) * T + t];
+                const R l1 = LU[(size_t)pq * T + t];
+                const R l0 = LU[(size_t)(pq - 1) * T + t];
+                if (in) {
+                    if (two) {
+                        acc1 = fma(l1, z, acc1);
+                        acc0 = fma(l0, z, acc0);
+                    } else {
+                        acc0 = fma(l1, z, acc0);
+                    }
                 }
             }
 #pragma unroll
@@ -532,7 +579,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 }
                 const R z0 = (y0 - acc0) / d0;
                 Yv[j * T + t] = z0;
-                if (upd_v && s_active[t]) {
+                if (upd_v && s_active[t] && !s_reset[t]) {
                     if (two) {
                         Va[bus * T + t] = va_old - (double)z0;
                         Vm[bus * T + t] = vm_old - (double)zl;
@@ -554,6 +601,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 for (int j = slot; j < N; j += SLOTS) a.aux_out[(size_t)b * N + a.perm[j]] = (double)Yv[j * T + t];
             return;
         }
+        if (tid < T && s_active[t] && !s_reset[t]) s_nupd[t]++;
     }
 
     // ---- tile layout -> boundary layout
@@ -646,8 +694,9 @@ static size_t lds_bytes(const HostPlan &h, const Config &c)
 static size_t lds_bytes(const HostPlan &h, const Config &c);
 static constexpr size_t kLdsLimit = 160 * 1024 - 8192;
 
-// Explicit tile/waves are validated; zeros pick the first candidate whose working columns
-// fit in LDS (larger tiles first: wider coalesced rows and fewer workgroups).
+// Explicit tile/waves are validated.  Zeros pick, in order of preference (8 waves: more
+// panels in flight per tile; larger tiles: wider coalesced rows), the first candidate of
+// which two workgroups fit in one CU's LDS, else the first that fits at all.
 static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c, std::string &err)
 {
     c.precision = o ? o->precision : PF_FP64;
@@ -660,13 +709,14 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
         err = "unsupported tile size for this precision"; return false;
     }
     if (waves != 0 && waves != 2 && waves != 4 && waves != 8) { err = "waves must be 2, 4 or 8"; return false; }
-    static const int cand64[][2] = {{8, 4}, {4, 8}, {8, 2}, {4, 4}, {4, 2}};
-    static const int cand32[][2] = {{16, 4}, {8, 8}, {16, 2}, {8, 4}, {8, 2}};
-    for (const auto &cw : (fp64 ? cand64 : cand32)) {
-        c.tile = tile ? tile : cw[0];
-        c.waves = waves ? waves : cw[1];
-        if (lds_bytes(h, c) <= kLdsLimit) return true;
-    }
+    static const int cand64[][2] = {{8, 8}, {4, 8}, {8, 4}, {4, 4}, {8, 2}, {4, 2}};
+    static const int cand32[][2] = {{16, 8}, {8, 8}, {16, 4}, {8, 4}, {16, 2}, {8, 2}};
+    for (const size_t limit : {(size_t)kLdsLimit / 2, (size_t)kLdsLimit})
+        for (const auto &cw : (fp64 ? cand64 : cand32)) {
+            c.tile = tile ? tile : cw[0];
+            c.waves = waves ? waves : cw[1];
+            if (lds_bytes(h, c) <= limit) return true;
+        }
     err = "the longest LU column (" + std::to_string(h.max_col) + " entries) does not fit in LDS for any "
           "supported tile/wave configuration";
     return false;
@@ -784,7 +834,7 @@ static int make_args(Plan *pl, const Config &c, int32_t batch, const double *ybu
 static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *sbus, const double *v0,
                double tol, int32_t max_iter, const pf_solve_opts *opts, void *workspace,
                size_t workspace_bytes, int mode, double *v_out, int32_t *iters_out, uint8_t *conv_out,
-               int8_t *status_out, double *aux, double *aux2, void *stream)
+               int8_t *status_out, double *aux, double *aux2, void *stream, const double *v_fb = nullptr)
 {
     Plan *pl = reinterpret_cast<Plan *>(plan_h);
     if (!pl) { set_error("null plan"); return PF_EINVAL; }
@@ -799,6 +849,7 @@ static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *
     const int rc = make_args(pl, c, batch, ybus, sbus, v0, tol, max_iter, workspace, workspace_bytes, mode, v_out,
                              iters_out, conv_out, status_out, aux, aux2, a, ntiles, lds);
     if (rc != PF_OK) return rc;
+    a.v_fb = v_fb;
     hipError_t e = launch(c, a, ntiles, lds, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) { set_error(std::string("kernel launch failed: ") + hipGetErrorString(e)); return PF_EDEVICE; }
     return PF_OK;
@@ -1223,6 +1274,18 @@ int pf_solve_batch(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus
     if (ybus_batched != 0) { set_error("per-instance Ybus values are not supported"); return PF_EINVAL; }
     return run(plan, batch, ybus, sbus, v0, tol, max_iter, opts, workspace, workspace_bytes, MODE_SOLVE,
                v_out, iters_out, converged_out, status_out, nullptr, nullptr, stream);
+}
+
+int pf_solve_batch_warm(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus_batched,
+                        const double *sbus, const double *v0, const double *v_fallback, double tol,
+                        int32_t max_iter, const pf_solve_opts *opts, void *workspace,
+                        size_t workspace_bytes, double *v_out, int32_t *iters_out, uint8_t *converged_out,
+                        int8_t *status_out, void *stream)
+{
+    if (ybus_batched != 0) { set_error("per-instance Ybus values are not supported"); return PF_EINVAL; }
+    if (!v_fallback) { set_error("null fallback start"); return PF_EINVAL; }
+    return run(plan, batch, ybus, sbus, v0, tol, max_iter, opts, workspace, workspace_bytes, MODE_SOLVE,
+               v_out, iters_out, converged_out, status_out, nullptr, nullptr, stream, v_fallback);
 }
 
 int pf_eval_mismatch(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,

@@ -169,14 +169,16 @@ class WarmStartNet:
 
     # ------------------------------------------------------------------ training
     def fit(self, x_all, y_all, n_train: int, epochs: int = 20, batch: int = 256, lr: float = 1e-3,
-            seed: int = 0, log=None) -> TrainReport:
+            seed: int = 0, log=None, lr_final: float | None = None) -> TrainReport:
         """x_all BF16 [S][2nf], y_all FP32 normalised [S][2nf] on the device; the first
-        n_train rows train, the rest validate."""
+        n_train rows train, the rest validate.  With lr_final the learning rate follows a
+        cosine from lr down to lr_final over all steps."""
         t = self.torch
         rng = np.random.default_rng(seed)
         rep = TrainReport(epochs=epochs, steps=0, seconds=0.0)
         t0 = time.perf_counter()
         S = int(x_all.shape[0])
+        total = max(1, epochs * max(0, (n_train - batch) // batch + 1))
         for ep in range(epochs):
             perm = t.from_numpy(rng.permutation(n_train)).to(self.device)
             acc = []
@@ -184,7 +186,10 @@ class WarmStartNet:
                 idx = perm[s0:s0 + batch]
                 xb = x_all.index_select(0, idx)
                 yb = y_all.index_select(0, idx)
-                acc.append(self.train_step(xb, yb, lr=lr))
+                step_lr = lr
+                if lr_final is not None:
+                    step_lr = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * rep.steps / total))
+                acc.append(self.train_step(xb, yb, lr=step_lr))
                 rep.steps += 1
             tl = float(t.stack(acc).sum(dim=1).mean().item()) if acc else float("nan")
             vl = float("nan")
@@ -268,22 +273,10 @@ def target_stats(y: np.ndarray):
 
 
 def solve_with_warm_start(plan: Plan, net: WarmStartNet, ybus, sbus, v_flat, tol=1e-8, max_iter=10,
-                          precision=PF_FP64, workspace=None, fallback=True):
-    """Warm-started solve with a flat-start re-solve of the instances that fail.
-    Returns (result, number of fallback instances)."""
-    t = net.torch
+                          precision=PF_FP64, workspace=None, fallback=True, **kw):
+    """Warm-started solve: the network predicts the start, and with fallback an instance that
+    fails from it restarts from the flat start inside the same kernel launch
+    (pf_solve_batch_warm).  Returns the result."""
     v0 = net.warm_v0(sbus, v_flat)
-    res = solve_batch(plan, ybus, sbus, v0, tol=tol, max_iter=max_iter, precision=precision, workspace=workspace)
-    n_fb = 0
-    if fallback:
-        bad = (res.converged == 0).nonzero().flatten()
-        n_fb = int(bad.numel())
-        if n_fb:
-            r2 = solve_batch(plan, ybus, sbus.index_select(0, bad).contiguous(),
-                             v_flat.index_select(0, bad).contiguous(), tol=tol, max_iter=max_iter,
-                             precision=precision, workspace=workspace)
-            res.v.index_copy_(0, bad, r2.v)
-            res.iters.index_copy_(0, bad, r2.iters + res.iters.index_select(0, bad))
-            res.converged.index_copy_(0, bad, r2.converged)
-            res.status.index_copy_(0, bad, r2.status)
-    return res, n_fb
+    return solve_batch(plan, ybus, sbus, v0, tol=tol, max_iter=max_iter, precision=precision,
+                       workspace=workspace, v_fallback=v_flat if fallback else None, **kw)

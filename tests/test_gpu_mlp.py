@@ -125,11 +125,11 @@ def test_warm_start_reduces_iterations():
     s_ev = torch.from_numpy(ev.sbus).to(DEV)
     v_ev = torch.from_numpy(ev.v0).to(DEV)
     flat = pf.solve_batch(plan, y, s_ev, v_ev)
-    warm, n_fb = ws.solve_with_warm_start(plan, net, y, s_ev, v_ev)
+    warm = ws.solve_with_warm_start(plan, net, y, s_ev, v_ev)
     fi = flat.iters.cpu().numpy(); wi = warm.iters.cpu().numpy()
     fc = flat.converged.cpu().numpy().astype(bool); wc = warm.converged.cpu().numpy().astype(bool)
     print(f"\nflat start mean iterations {fi[fc].mean():.3f}, warm start {wi[wc].mean():.3f}, "
-          f"fallbacks {n_fb}, train {rep.seconds:.1f} s")
+          f"train {rep.seconds:.1f} s")
     assert wc[fc].all()
     assert wi[fc].mean() < fi[fc].mean()
     dv = np.abs(warm.v.cpu().numpy()[fc] - flat.v.cpu().numpy()[fc]).max()

@@ -324,3 +324,33 @@ def test_fp32_lu_converges_to_fp64_answer(systems, name, B):
     # the FP64 mismatch at the returned V meets the tolerance
     F, nf = pf.eval_mismatch(plan, y, s, rg.v)
     assert (nf.cpu().numpy()[both] < 1e-8).all()
+
+
+def test_warm_entry_point_restarts_failed_instances(systems):
+    """pf_solve_batch_warm: instances whose start is broken (|V| = 0 gives a non-finite
+    mismatch at once; a far-off start exhausts max_iter or diverges) restart from the
+    fallback inside the kernel and end exactly where the plain flat-start solve ends; the
+    other instances are untouched by the fallback."""
+    g, yb, osys, plan = systems["c4_100bus"]
+    sc = gg.make_scenarios(g, 96, 31, "mc")
+    y, s, vflat = to_dev(yb, sc)
+    ref = pf.solve_batch(plan, y, s, vflat)
+    v0 = vflat.clone()
+    v0[0:32, :, 0] = 0.0                                   # non-finite at iteration 0
+    v0[32:64, 1:, 1] = 3.0                                 # far-off angles
+    for prec in (pf.PF_FP64, pf.PF_FP32_LU):
+        r0 = pf.solve_batch(plan, y, s, vflat, precision=prec)
+        r = pf.solve_batch(plan, y, s, v0, precision=prec, v_fallback=vflat)
+        torch.cuda.synchronize()
+        for sl in (slice(0, 32), slice(64, 96)):
+            assert torch.equal(r.converged[sl], r0.converged[sl])
+            assert torch.equal(r.status[sl], r0.status[sl])
+            assert torch.equal(r.v[sl], r0.v[sl]) and torch.equal(r.iters[sl], r0.iters[sl])
+        # far-off starts: converged from there (possibly to another power-flow solution) or
+        # restarted from the flat start, so never worse than the flat start alone
+        assert bool((r.converged[32:64] >= r0.converged[32:64]).all())
+    # without the fallback the broken starts fail
+    rn = pf.solve_batch(plan, y, s, v0)
+    torch.cuda.synchronize()
+    assert not bool(rn.converged[0:32].any())
+    assert bool(ref.converged[0:32].all())
