@@ -67,7 +67,7 @@ typedef struct {
                               voltage update in FP64 (inexact Newton)                      */
     int32_t tile;          /* instances per workgroup: 4, 8 or 16 (FP64), 8, 16 or 32
                               (FP32-LU); 0 = automatic                                     */
-    int32_t waves;         /* wavefronts per workgroup (2, 4 or 8); 0 = automatic           */
+    int32_t waves;         /* wavefronts per workgroup (2, 4, 8 or 16); 0 = automatic       */
     int32_t schedule;      /* order in which wavefronts take the panels (single columns and
                               the angle/|V| column pairs of PQ buses): 0 = by level of the
                               column DAG (default), 1 = elimination order; both are
@@ -108,6 +108,13 @@ int pf_plan_lu_pattern(pf_plan plan, int32_t *col_ptr, int32_t *row_idx, int32_t
 
 /* Workspace bytes pf_solve_batch needs for `batch` instances with `opts` (NULL = default). */
 size_t pf_workspace_bytes(pf_plan plan, int32_t batch, const pf_solve_opts *opts);
+
+/*
+ * pf_resolve_opts: the configuration pf_solve_batch would use for batch instances with opts
+ * (NULL = defaults): zero tile/waves are replaced by the automatic choice.  PF_EINVAL
+ * for invalid options or when nothing fits in LDS.
+ */
+int pf_resolve_opts(pf_plan plan, int32_t batch, const pf_solve_opts *opts, pf_solve_opts *out);
 
 /*
  * pf_solve_batch -- `batch` Newton-Raphson power flows on the plan's pattern (Sec. 3).

@@ -27,7 +27,8 @@ EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
             "pf_eval_step", "pf_plan_destroy", "pf_last_error", "pf_mlp_gemm",
             "pf_mlp_act_backward", "pf_mlp_mse", "pf_mlp_adam", "pf_mlp_to_bf16",
             "pf_mlp_features", "pf_mlp_warm_v0", "pf_queue_create", "pf_queue_add",
-            "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune", "pf_solve_batch_warm"]
+            "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune", "pf_solve_batch_warm",
+            "pf_resolve_opts"]
 
 
 class PfError(RuntimeError):
@@ -98,6 +99,7 @@ def lib():
         L.pf_solve_batch_warm.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, _vp,
                                           ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Opts), _vp,
                                           ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
+        L.pf_resolve_opts.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_Opts), ctypes.POINTER(_Opts)]
         L.pf_queue_create.argtypes = [ctypes.POINTER(_vp)]
         L.pf_queue_add.argtypes = [_vp, _vp, i32, _vp, _vp, _vp, ctypes.c_double, i32,
                                    ctypes.POINTER(_Opts), _vp, _vp, _vp, _vp, _vp]
@@ -174,6 +176,13 @@ class Plan:
         _check(lib().pf_plan_lu_pattern(self._h, cp.ctypes.data_as(_i32p), ri.ctypes.data_as(_i32p),
                                         lv.ctypes.data_as(_i32p)), "pf_plan_lu_pattern")
         return cp, ri, lv
+
+    def resolve(self, batch: int, precision=PF_FP64, tile=0, waves=0, schedule=0) -> dict:
+        """The configuration a solve of batch instances would use (pf_resolve_opts)."""
+        o = _Opts()
+        _check(lib().pf_resolve_opts(self._h, int(batch), ctypes.byref(_Opts(precision, tile, waves, schedule)),
+                                     ctypes.byref(o)), "pf_resolve_opts")
+        return {"precision": o.precision, "tile": o.tile, "waves": o.waves, "schedule": o.schedule}
 
     def workspace_bytes(self, batch: int, precision=PF_FP64, tile=0, waves=0) -> int:
         o = _Opts(precision, tile, waves)

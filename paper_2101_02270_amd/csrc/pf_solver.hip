@@ -639,7 +639,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
 // grid always drains.
 template <typename R, int T, int NW>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void nr_queue_kernel(
-    const KArgs *items, const int *prefix, int nitems, int *counter)
+    const KArgs *__restrict__ items, const int *__restrict__ prefix, int nitems, int *counter)
 {
     __shared__ int s_tile;
     const int total = prefix[nitems];
@@ -694,10 +694,15 @@ static size_t lds_bytes(const HostPlan &h, const Config &c)
 static size_t lds_bytes(const HostPlan &h, const Config &c);
 static constexpr size_t kLdsLimit = 160 * 1024 - 8192;
 
-// Explicit tile/waves are validated.  Zeros pick, in order of preference (8 waves: more
-// panels in flight per tile; larger tiles: wider coalesced rows), the first candidate of
-// which two workgroups fit in one CU's LDS, else the first that fits at all.
-static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c, std::string &err)
+// Explicit tile/waves are validated.  A zero picks the value that minimises a latency
+// model of the solve: a tile's time grows with the panels each wavefront handles in turn
+// (n_panels / waves) and mildly with the rows per lane (1 + T/32); tiles run in
+// max(1, tiles / resident workgroups) generations, where the resident workgroups per CU are
+// limited by LDS and by the 16 wavefronts per CU that four waves per SIMD allow.  Within
+// 10% of the lowest cost, 8-wave workgroups are preferred (measured best when the model
+// ties), then more resident workgroups.  batch <= 0 assumes a batch much larger than the GPU.
+static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c, std::string &err,
+                           int64_t batch = 0)
 {
     c.precision = o ? o->precision : PF_FP64;
     c.schedule = o ? o->schedule : 0;
@@ -708,15 +713,41 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
     if (tile != 0 && !(fp64 ? (tile == 4 || tile == 8 || tile == 16) : (tile == 8 || tile == 16 || tile == 32))) {
         err = "unsupported tile size for this precision"; return false;
     }
-    if (waves != 0 && waves != 2 && waves != 4 && waves != 8) { err = "waves must be 2, 4 or 8"; return false; }
-    static const int cand64[][2] = {{8, 8}, {4, 8}, {8, 4}, {4, 4}, {8, 2}, {4, 2}};
-    static const int cand32[][2] = {{16, 8}, {8, 8}, {16, 4}, {8, 4}, {16, 2}, {8, 2}};
-    for (const size_t limit : {(size_t)kLdsLimit / 2, (size_t)kLdsLimit})
-        for (const auto &cw : (fp64 ? cand64 : cand32)) {
-            c.tile = tile ? tile : cw[0];
-            c.waves = waves ? waves : cw[1];
-            if (lds_bytes(h, c) <= limit) return true;
+    if (waves != 0 && waves != 2 && waves != 4 && waves != 8 && waves != 16) {
+        err = "waves must be 2, 4, 8 or 16"; return false;
+    }
+    static const int tiles64[] = {4, 8, 16}, tiles32[] = {8, 16, 32}, wv[] = {2, 4, 8, 16};
+    const double b = batch > 0 ? (double)batch : 1e9;
+    struct Cand { int tile, waves, wg; double cost; };
+    std::vector<Cand> cands;
+    for (const int tc : (fp64 ? tiles64 : tiles32))
+        for (const int wc : wv) {
+            if ((tile && tc != tile) || (waves && wc != waves)) continue;
+            Config k = c;
+            k.tile = tc;
+            k.waves = wc;
+            const size_t lds = lds_bytes(h, k);
+            if (lds > kLdsLimit) continue;
+            const int wg = (int)std::max<size_t>(1, std::min<size_t>(kLdsLimit / std::max<size_t>(lds, 1), 16 / wc));
+            const double gens = std::max(1.0, std::ceil(b / tc) / (256.0 * wg));
+            cands.push_back(Cand{tc, wc, wg, gens / wc * (1.0 + tc / 32.0)});
         }
+    if (!cands.empty()) {
+        double lo = cands[0].cost;
+        for (const Cand &k : cands) lo = std::min(lo, k.cost);
+        const Cand *pick = nullptr;
+        for (const Cand &k : cands) {
+            if (k.cost > lo * 1.1) continue;
+            if (!pick) { pick = &k; continue; }
+            const bool k8 = k.waves == 8, p8 = pick->waves == 8;
+            if (k8 != p8) { if (k8) pick = &k; continue; }
+            if (k.wg != pick->wg) { if (k.wg > pick->wg) pick = &k; continue; }
+            if (k.cost < pick->cost) pick = &k;
+        }
+        c.tile = pick->tile;
+        c.waves = pick->waves;
+        return true;
+    }
     err = "the longest LU column (" + std::to_string(h.max_col) + " entries) does not fit in LDS for any "
           "supported tile/wave configuration";
     return false;
@@ -744,6 +775,7 @@ static hipError_t launch_t(const KArgs &a, int grid, size_t lds, hipStream_t st)
     switch (c.waves) {                                                         \
     case 2: return launch_t<R, T, 2>(a, grid, lds, st);                        \
     case 4: return launch_t<R, T, 4>(a, grid, lds, st);                        \
+    case 16: return launch_t<R, T, 16>(a, grid, lds, st);                      \
     default: return launch_t<R, T, 8>(a, grid, lds, st);                       \
     }
 
@@ -753,6 +785,7 @@ static const void *queue_kernel_nw(int waves)
 {
     if (waves == 2) return reinterpret_cast<const void *>(nr_queue_kernel<R, T, 2>);
     if (waves == 4) return reinterpret_cast<const void *>(nr_queue_kernel<R, T, 4>);
+    if (waves == 16) return reinterpret_cast<const void *>(nr_queue_kernel<R, T, 16>);
     return reinterpret_cast<const void *>(nr_queue_kernel<R, T, 8>);
 }
 
@@ -842,7 +875,7 @@ static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *
     if (batch == 0) return PF_OK;
     Config c;
     std::string err;
-    if (!resolve_config(pl->h, opts, c, err)) { set_error(err); return PF_EINVAL; }
+    if (!resolve_config(pl->h, opts, c, err, batch)) { set_error(err); return PF_EINVAL; }
     KArgs a;
     int ntiles = 0;
     size_t lds = 0;
@@ -1260,9 +1293,24 @@ size_t pf_workspace_bytes(pf_plan plan, int32_t batch, const pf_solve_opts *opts
     if (!pl || batch <= 0) return 0;
     Config c;
     std::string err;
-    if (!resolve_config(pl->h, opts, c, err)) { set_error(err); return 0; }
+    if (!resolve_config(pl->h, opts, c, err, batch)) { set_error(err); return 0; }
     const TileLayout L = tile_layout(pl->h, c);
     return L.bytes * (size_t)((batch + c.tile - 1) / c.tile);
+}
+
+int pf_resolve_opts(pf_plan plan, int32_t batch, const pf_solve_opts *opts, pf_solve_opts *out)
+{
+    Plan *pl = reinterpret_cast<Plan *>(plan);
+    if (!pl || !out) { set_error("null argument"); return PF_EINVAL; }
+    Config c;
+    std::string err;
+    if (!resolve_config(pl->h, opts, c, err, batch)) { set_error(err); return PF_EINVAL; }
+    std::memset(out, 0, sizeof(*out));
+    out->precision = c.precision;
+    out->tile = c.tile;
+    out->waves = c.waves;
+    out->schedule = c.schedule;
+    return PF_OK;
 }
 
 int pf_solve_batch(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus_batched,
@@ -1348,7 +1396,7 @@ int pf_queue_add(pf_queue queue, pf_plan plan, int32_t batch, const double *ybus
     if (pl->dev_mem && pl->device != q->device) { set_error("plan and queue are on different devices"); return PF_EDEVICE; }
     Config c;
     std::string err;
-    if (!resolve_config(pl->h, opts, c, err)) { set_error(err); return PF_EINVAL; }
+    if (!resolve_config(pl->h, opts, c, err, batch)) { set_error(err); return PF_EINVAL; }
     if (lds_bytes(pl->h, c) > kLdsLimit) { set_error("configuration does not fit in LDS"); return PF_EINVAL; }
     QueueItem it{pl, c, batch, ybus, sbus, v0, tol, max_iter, v_out, iters_out, converged_out, status_out,
                  reinterpret_cast<unsigned long long *>(done_ticks_out)};
@@ -1415,7 +1463,10 @@ int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
     if (batch <= 0 || reps <= 0) { set_error("batch and reps must be positive"); return PF_EINVAL; }
     if (!ybus || !sbus || !v0) { set_error("null input pointer"); return PF_EINVAL; }
     if (precision != PF_FP64 && precision != PF_FP32_LU) { set_error("unknown precision"); return PF_EINVAL; }
-    if (waves != 0 && waves != 2 && waves != 4 && waves != 8) { set_error("waves must be 0, 2, 4 or 8"); return PF_EINVAL; }
+    if (waves != 0 && waves != 2 && waves != 4 && waves != 8 && waves != 16) {
+        set_error("waves must be 0, 2, 4, 8 or 16");
+        return PF_EINVAL;
+    }
     if (max_iter < 0 || !(tol >= 0.0)) { set_error("invalid tol or max_iter"); return PF_EINVAL; }
     if (!pl->dev_mem) {
         const int rcu = upload(pl);
@@ -1438,7 +1489,7 @@ int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
     }
     // candidate configurations that fit in LDS
     std::vector<pf_solve_opts> cand;
-    const int tiles64[] = {4, 8, 16}, tiles32[] = {8, 16, 32}, wv[] = {2, 4, 8};
+    const int tiles64[] = {4, 8, 16}, tiles32[] = {8, 16, 32}, wv[] = {2, 4, 8, 16};
     for (int ti = 0; ti < 3; ti++)
         for (int w : wv) {
             if (waves && w != waves) continue;
