@@ -221,6 +221,31 @@ def queue_variant(steps, warmup, log, precision_name="fp32lu"):
             "per_grid": per_grid}
 
 
+def n_minus_1_variant(steps, warmup):
+    """The 1,350-bus workload with one random non-bridge branch out per scenario: every
+    instance carries its own Ybus values on the shared pattern (ybus_batched = 1)."""
+    import torch
+    import gridgen as gg
+    import paper_2101_02270_amd as pf
+    dev = torch.device("cuda", 0)
+    (g, yb, sc), = gg.workload("c1")
+    plan = pf.Plan.from_ybus(yb, g.bus_type)
+    nb = gg.non_bridge_branches(g)
+    out = np.random.default_rng(7).choice(nb, sc.batch)
+    yv = torch.from_numpy(gg.ybus_outage_values(g, yb, out)).to(dev)
+    s = torch.from_numpy(sc.sbus).to(dev)
+    v = torch.from_numpy(sc.v0).to(dev)
+    res = {}
+    for prec, name in ((pf.PF_FP64, "fp64"), (pf.PF_FP32_LU, "fp32lu")):
+        dt, r = timed_solves(lambda: pf.solve_batch(plan, yv, s, v, precision=prec), steps, warmup)
+        conv = r.converged.cpu().numpy().astype(bool)
+        res[name] = {"flows_per_s": round(int(conv.sum()) / dt, 1), "ms": round(dt * 1e3, 3),
+                     "converged_fraction": round(float(conv.mean()), 5),
+                     "iterations_mean": round(float(r.iters.cpu().numpy()[conv].mean()), 4)}
+    return {"workload": "1350-bus grid, 10,000 Monte Carlo scenarios, each with one random non-bridge "
+                        "branch out (per-instance Ybus values on the shared pattern)", **res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -345,6 +370,8 @@ def main():
         res["variants"] = warm_start_variants(max(2, args.steps // 2), 1, args.epochs, log)
         log("[bench] variants: four-grid queue with tuned configurations")
         res["variants"]["multi_grid"] = queue_variant(max(2, args.steps // 2), 1, log)
+        log("[bench] variants: N-1 contingencies (per-instance Ybus values)")
+        res["variants"]["n_minus_1"] = n_minus_1_variant(max(2, args.steps // 2), 1)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(g, yb, sc, tol, max_iter)

@@ -215,6 +215,56 @@ def ybus(grid: Grid) -> Ybus:
     return Ybus(n=n, row_ptr=row_ptr, col_idx=c_idx, val=acc)
 
 
+def ybus_outage(grid: Grid, k: int) -> Ybus:
+    """Ybus of the grid with branch k out of service, on the full grid's pattern: the
+    branch's pi-model contributions are subtracted, so its off-diagonal entries become
+    explicit zeros (N-1 contingency cases share one sparsity pattern)."""
+    full = ybus(grid)
+    return Ybus(n=grid.n, row_ptr=full.row_ptr, col_idx=full.col_idx,
+                val=ybus_outage_values(grid, full, np.array([k]))[0])
+
+
+def ybus_outage_values(grid: Grid, full: Ybus, outages) -> np.ndarray:
+    """complex128 [len(outages)][nnz]: the full Ybus values with branch outages[i] removed."""
+    def pos(i, j):
+        row = full.col_idx[full.row_ptr[i]:full.row_ptr[i + 1]]
+        return full.row_ptr[i] + int(np.searchsorted(row, j))
+    out = np.repeat(full.val[None, :], len(outages), axis=0)
+    for i, k in enumerate(np.asarray(outages, dtype=np.int64)):
+        f, t = int(grid.f[k]), int(grid.t[k])
+        ys = 1.0 / (grid.r[k] + 1j * grid.x[k])
+        ysh = 0.5j * grid.b[k]
+        out[i, pos(f, f)] -= ys + ysh
+        out[i, pos(t, t)] -= ys + ysh
+        out[i, pos(f, t)] = 0.0
+        out[i, pos(t, f)] = 0.0
+    return out
+
+
+def non_bridge_branches(grid: Grid) -> np.ndarray:
+    """Branches whose outage leaves the grid connected (so every N-1 case keeps a
+    solvable power flow structure)."""
+    out = []
+    for k in range(grid.f.size):
+        adj = [[] for _ in range(grid.n)]
+        for e in range(grid.f.size):
+            if e != k:
+                adj[grid.f[e]].append(grid.t[e])
+                adj[grid.t[e]].append(grid.f[e])
+        seen = np.zeros(grid.n, dtype=bool)
+        stack = [0]
+        seen[0] = True
+        while stack:
+            u = stack.pop()
+            for w in adj[u]:
+                if not seen[w]:
+                    seen[w] = True
+                    stack.append(w)
+        if seen.all():
+            out.append(k)
+    return np.asarray(out, dtype=np.int64)
+
+
 # --------------------------------------------------------------------------- scenarios
 def flat_start(grid: Grid, batch: int) -> np.ndarray:
     v0 = np.zeros((batch, grid.n, 2))

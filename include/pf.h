@@ -118,8 +118,10 @@ int pf_resolve_opts(pf_plan plan, int32_t batch, const pf_solve_opts *opts, pf_s
 
 /*
  * pf_solve_batch -- `batch` Newton-Raphson power flows on the plan's pattern (Sec. 3).
- *   ybus [device]      nnz_y complex Ybus values in the pattern's order
- *   ybus_batched       must be 0 (one Ybus shared by every instance)
+ *   ybus [device]      nnz_y complex Ybus values in the pattern's order, shared by every
+ *                      instance (ybus_batched = 0), or batch x nnz_y values, one set per
+ *                      instance on the same pattern (ybus_batched = 1: N-1 contingency
+ *                      cases, where an outaged branch leaves explicit zeros; Sec. 2)
  *   sbus [device]      [batch][n_bus] complex specified injections (pu): P at PV and PQ
  *                      buses, Q at PQ buses are used; the rest is ignored
  *   v0 [device]        [batch][n_bus][2] initial (|V|, angle in rad); |V| at PV and REF
@@ -270,6 +272,21 @@ enum { PF_TUNE_FORCE = 1 };
 int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus, const double *v0, double tol,
             int32_t max_iter, int32_t precision, int32_t waves, int32_t reps, int32_t flags,
             pf_solve_opts *best_out, double *best_ms_out, void *stream);
+
+/*
+ * pf_branch_flows: branch power flows and losses at voltages v (e.g. a solve's v_out), the
+ * quantities a batch of scenarios is run for.  Pi-model branches: series admittance
+ * 1/(r + jx), total line charging b_total split half per end.
+ *   from_bus, to_bus [device]  n_branch bus indices (outside [0, n_bus): NaN flows)
+ *   r, x, b_total [device]     n_branch per-unit parameters
+ *   v [device]                 batch x n_bus x 2 (|V|, angle), as pf_solve_batch's v_out
+ *   s_from, s_to [device]      out, batch x n_branch x 2 complex S at each end (pu)
+ *   loss [device]              out, batch x 2 complex sum of S_from + S_to, or NULL
+ * Stream-ordered; the caller owns every buffer.
+ */
+int pf_branch_flows(int32_t n_bus, int32_t n_branch, const int32_t *from_bus, const int32_t *to_bus,
+                    const double *r, const double *x, const double *b_total, int32_t batch, const double *v,
+                    double *s_from, double *s_to, double *loss, void *stream);
 
 /* Release the plan and its device memory. */
 void pf_plan_destroy(pf_plan plan);

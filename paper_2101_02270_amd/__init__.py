@@ -28,7 +28,7 @@ EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
             "pf_mlp_act_backward", "pf_mlp_mse", "pf_mlp_adam", "pf_mlp_to_bf16",
             "pf_mlp_features", "pf_mlp_warm_v0", "pf_queue_create", "pf_queue_add",
             "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune", "pf_solve_batch_warm",
-            "pf_resolve_opts"]
+            "pf_resolve_opts", "pf_branch_flows"]
 
 
 class PfError(RuntimeError):
@@ -99,6 +99,7 @@ def lib():
         L.pf_solve_batch_warm.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, _vp,
                                           ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Opts), _vp,
                                           ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
+        L.pf_branch_flows.argtypes = [i32, i32, _vp, _vp, _vp, _vp, _vp, i32, _vp, _vp, _vp, _vp, _vp]
         L.pf_resolve_opts.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_Opts), ctypes.POINTER(_Opts)]
         L.pf_queue_create.argtypes = [ctypes.POINTER(_vp)]
         L.pf_queue_add.argtypes = [_vp, _vp, i32, _vp, _vp, _vp, ctypes.c_double, i32,
@@ -234,11 +235,15 @@ def _workspace(plan: Plan, batch, opts, workspace):
     return workspace, _vp(aligned), avail
 
 
-def _ybus_view(plan: Plan, ybus):
+def _ybus_view(plan: Plan, ybus, batch=None):
+    """Shared Ybus values [nnz_y] (complex128) or [nnz_y][2], or with batch per-instance
+    values [batch][nnz_y] / [batch][nnz_y][2].  Returns (pointer, tensor, batched flag)."""
     torch = _torch()
     if ybus.dtype == torch.complex128:
         ybus = torch.view_as_real(ybus)
-    return _dev_ptr(ybus, torch.float64, (plan.nnz_y, 2), "ybus"), ybus
+    if ybus.dim() == 3:
+        return _dev_ptr(ybus, torch.float64, (batch, plan.nnz_y, 2), "ybus"), ybus, 1
+    return _dev_ptr(ybus, torch.float64, (plan.nnz_y, 2), "ybus"), ybus, 0
 
 
 def _as_pairs(x, name):
@@ -252,13 +257,14 @@ def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 1
                 precision: int = PF_FP64, tile: int = 0, waves: int = 0, workspace=None,
                 stream=None, out: Optional[Result] = None, schedule: int = 0,
                 v_fallback=None) -> Result:
-    """Run pf_solve_batch on device tensors: ybus complex128 [nnz_y], sbus complex128 [B][n],
+    """Run pf_solve_batch on device tensors: ybus complex128 [nnz_y] (or [B][nnz_y]: one set of
+    values per instance), sbus complex128 [B][n],
     v0 float64 [B][n][2].  With v_fallback (same shape as v0) pf_solve_batch_warm runs
     instead: instances that fail from v0 restart once from v_fallback inside the kernel.
     Returns device tensors (valid once the stream synchronises)."""
     torch = _torch()
     B = int(v0.shape[0])
-    yp, _ = _ybus_view(plan, ybus)
+    yp, _, yb_batched = _ybus_view(plan, ybus, B)
     s2 = _as_pairs(sbus, "sbus")
     sp = _dev_ptr(s2, torch.float64, (B, plan.n, 2), "sbus")
     vp = _dev_ptr(v0, torch.float64, (B, plan.n, 2), "v0")
@@ -272,12 +278,12 @@ def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 1
     outs = (_vp(out.v.data_ptr()), _vp(out.iters.data_ptr()), _vp(out.converged.data_ptr()),
             _vp(out.status.data_ptr()), _stream_ptr(stream))
     if v_fallback is None:
-        rc = lib().pf_solve_batch(plan._h, B, yp, 0, sp, vp, float(tol), int(max_iter),
+        rc = lib().pf_solve_batch(plan._h, B, yp, yb_batched, sp, vp, float(tol), int(max_iter),
                                   ctypes.byref(opts), wp, avail, *outs)
         _check(rc, "pf_solve_batch")
     else:
         fp = _dev_ptr(v_fallback, torch.float64, (B, plan.n, 2), "v_fallback")
-        rc = lib().pf_solve_batch_warm(plan._h, B, yp, 0, sp, vp, fp, float(tol), int(max_iter),
+        rc = lib().pf_solve_batch_warm(plan._h, B, yp, yb_batched, sp, vp, fp, float(tol), int(max_iter),
                                        ctypes.byref(opts), wp, avail, *outs)
         _check(rc, "pf_solve_batch_warm")
     out._workspace = workspace
@@ -288,7 +294,7 @@ def _eval(fn, plan: Plan, ybus, sbus, v, out_shape, precision, tile, waves, extr
           workspace=None, stream=None):
     torch = _torch()
     B = int(v.shape[0])
-    yp, _ = _ybus_view(plan, ybus)
+    yp, _, _ = _ybus_view(plan, ybus)
     s2 = _as_pairs(sbus, "sbus")
     sp = _dev_ptr(s2, torch.float64, (B, plan.n, 2), "sbus")
     vp = _dev_ptr(v, torch.float64, (B, plan.n, 2), "v")
@@ -333,7 +339,7 @@ def tune(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
     ({"precision", "tile", "waves", "schedule"}, mean ms per solve)."""
     torch = _torch()
     B = int(v0.shape[0])
-    yp, _ = _ybus_view(plan, ybus)
+    yp, _, _ = _ybus_view(plan, ybus)
     sp = _dev_ptr(_as_pairs(sbus, "sbus"), torch.float64, (B, plan.n, 2), "sbus")
     vp = _dev_ptr(v0, torch.float64, (B, plan.n, 2), "v0")
     best = _Opts()
@@ -363,7 +369,7 @@ class Queue:
             ticks: bool = True) -> Result:
         torch = _torch()
         B = int(v0.shape[0])
-        yp, yv = _ybus_view(plan, ybus)
+        yp, yv, _ = _ybus_view(plan, ybus)
         s2 = _as_pairs(sbus, "sbus")
         sp = _dev_ptr(s2, torch.float64, (B, plan.n, 2), "sbus")
         vp = _dev_ptr(v0, torch.float64, (B, plan.n, 2), "v0")
@@ -404,3 +410,24 @@ class Queue:
             self.close()
         except Exception:
             pass
+
+
+def branch_flows(from_bus, to_bus, r, x, b_total, n_bus: int, v, losses: bool = True, stream=None):
+    """pf_branch_flows on device tensors: from_bus/to_bus int32 [m], r/x/b_total float64 [m],
+    v float64 [B][n_bus][2].  Returns (s_from, s_to, loss) complex128 tensors ([B][m],
+    [B][m], [B] or None)."""
+    torch = _torch()
+    m = int(from_bus.shape[0])
+    B = int(v.shape[0])
+    dev = v.device
+    sf = torch.empty((B, m, 2), dtype=torch.float64, device=dev)
+    st = torch.empty((B, m, 2), dtype=torch.float64, device=dev)
+    loss = torch.empty((B, 2), dtype=torch.float64, device=dev) if losses else None
+    rc = lib().pf_branch_flows(int(n_bus), m, _dev_ptr(from_bus, torch.int32, (m,), "from_bus"),
+                               _dev_ptr(to_bus, torch.int32, (m,), "to_bus"), _dev_ptr(r, torch.float64, (m,), "r"),
+                               _dev_ptr(x, torch.float64, (m,), "x"), _dev_ptr(b_total, torch.float64, (m,), "b_total"),
+                               B, _dev_ptr(v, torch.float64, (B, n_bus, 2), "v"), _vp(sf.data_ptr()),
+                               _vp(st.data_ptr()), _vp(loss.data_ptr()) if losses else None, _stream_ptr(stream))
+    _check(rc, "pf_branch_flows")
+    return (torch.view_as_complex(sf), torch.view_as_complex(st),
+            torch.view_as_complex(loss) if losses else None)

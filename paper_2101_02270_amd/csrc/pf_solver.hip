@@ -38,6 +38,7 @@
 #include <vector>
 
 #include "pf_internal.h"
+#include "pf_math.h"
 
 namespace pf {
 
@@ -51,7 +52,8 @@ constexpr int UPD_GROUP = 4;     // column updates whose operand loads are issue
 struct KArgs {
     DevPlan p;
     const int32_t *perm;        // position -> unknown (device)
-    const double *ybus;         // [nnzy][2]
+    const double *ybus;         // [nnzy][2], or [B][nnzy][2] with ybus_stride = 2 nnzy
+    size_t ybus_stride;         // doubles between instances' Ybus values (0: shared)
     const double *sbus;         // [B][n][2]
     const double *v0;           // [B][n][2]
     const double *v_fb;         // [B][n][2] restart point after a failed first attempt (may be null)
@@ -69,48 +71,6 @@ struct KArgs {
     const unsigned long long *t0;          // start tick the completion ticks are relative to
     int sched;                  // 0: level order, 1: elimination order
 };
-
-// sin and cos of a voltage angle.  Reduction x = k pi/2 + r with k = rint(2x/pi) and
-// pi/2 split into three doubles (c1 = RN(pi/2), c2 = RN(pi/2 - c1), c3 = RN(pi/2 - c1 - c2)),
-// each step one fused multiply-add; then the Taylor series of sin r (to r^17) and cos r (to
-// r^18) on |r| <= pi/4, whose truncation error is below 1e-19, and the quadrant k mod 4.
-// Absolute error a few ulp for |x| < 2^20 pi/2; larger angles (only seen in diverging
-// solves) keep a finite but less accurate result, and NaN propagates.  A short path with
-// few live registers: the general library routine carries a long-argument reduction.
-__device__ __forceinline__ void sincos_angle(double x, double *sn, double *cs)
-{
-    constexpr double two_over_pi = 0x1.45f306dc9c883p-1;
-    constexpr double c1 = 0x1.921fb54442d18p+0, c2 = 0x1.1a62633145c07p-54, c3 = -0x1.f1976b7ed8fbcp-110;
-    const double k = rint(x * two_over_pi);
-    double r = fma(-k, c1, x);
-    r = fma(-k, c2, r);
-    r = fma(-k, c3, r);
-    const double r2 = r * r;
-    // (-1)^m / (2m+1)!  and  (-1)^m / (2m)!
-    double ps = 2.8114572543455206e-15;
-    ps = fma(ps, r2, -7.647163731819816e-13);
-    ps = fma(ps, r2, 1.6059043836821613e-10);
-    ps = fma(ps, r2, -2.505210838544172e-08);
-    ps = fma(ps, r2, 2.7557319223985893e-06);
-    ps = fma(ps, r2, -0.0001984126984126984);
-    ps = fma(ps, r2, 0.008333333333333333);
-    ps = fma(ps, r2, -0.16666666666666666);
-    const double s = fma(r * r2, ps, r);
-    double pc = -1.5619206968586225e-16;
-    pc = fma(pc, r2, 4.779477332387385e-14);
-    pc = fma(pc, r2, -1.1470745597729725e-11);
-    pc = fma(pc, r2, 2.08767569878681e-09);
-    pc = fma(pc, r2, -2.755731922398589e-07);
-    pc = fma(pc, r2, 2.48015873015873e-05);
-    pc = fma(pc, r2, -0.001388888888888889);
-    pc = fma(pc, r2, 0.041666666666666664);
-    pc = fma(pc, r2, -0.5);
-    const double c = fma(r2, pc, 1.0);
-    const int q = (int)((long long)fmin(fmax(k, -0x1p52), 0x1p52) & 3);
-    const double s_out = (q & 1) ? c : s, c_out = (q & 1) ? s : c;
-    *sn = (q & 2) ? -s_out : s_out;
-    *cs = ((q + 1) & 2) ? -c_out : c_out;
-}
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -243,6 +203,8 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         // diagonal dS_i/dangle_i = j (S_i - |V_i|^2 conj Y_ii), dS_i/d|V_i| = S_i / |V_i| +
         // |V_i| conj Y_ii.  P rows take the real part, Q rows the imaginary part.
         const bool build = a.mode != MODE_MISMATCH;
+        // this instance's Ybus values (padding lanes of the last tile read instance 0's)
+        const double2 *yrow = reinterpret_cast<const double2 *>(a.ybus + (valid ? (size_t)b * a.ybus_stride : 0));
         double mx = 0.0;
         int bad = 0;
         for (int i = slot; i < n; i += SLOTS) {
@@ -252,7 +214,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             int qdg = -1;
             for (int q = P.yrp[i]; q < P.yrp[i + 1]; q++) {
                 const int k = P.yci[q];
-                const double2 y = reinterpret_cast<const double2 *>(a.ybus)[q];
+                const double2 y = yrow[q];
                 const double2 v = Vc[k * T + t];
                 const double cr = y.x * v.x - y.y * v.y, ci = y.x * v.y + y.y * v.x;     // Y_ik V_k
                 ir += cr;
@@ -867,7 +829,8 @@ static int make_args(Plan *pl, const Config &c, int32_t batch, const double *ybu
 static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *sbus, const double *v0,
                double tol, int32_t max_iter, const pf_solve_opts *opts, void *workspace,
                size_t workspace_bytes, int mode, double *v_out, int32_t *iters_out, uint8_t *conv_out,
-               int8_t *status_out, double *aux, double *aux2, void *stream, const double *v_fb = nullptr)
+               int8_t *status_out, double *aux, double *aux2, void *stream, const double *v_fb = nullptr,
+               int ybus_batched = 0)
 {
     Plan *pl = reinterpret_cast<Plan *>(plan_h);
     if (!pl) { set_error("null plan"); return PF_EINVAL; }
@@ -883,6 +846,7 @@ static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *
                              iters_out, conv_out, status_out, aux, aux2, a, ntiles, lds);
     if (rc != PF_OK) return rc;
     a.v_fb = v_fb;
+    a.ybus_stride = ybus_batched ? (size_t)2 * pl->h.nnzy : 0;
     hipError_t e = launch(c, a, ntiles, lds, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) { set_error(std::string("kernel launch failed: ") + hipGetErrorString(e)); return PF_EDEVICE; }
     return PF_OK;
@@ -1319,9 +1283,9 @@ int pf_solve_batch(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus
                    double *v_out, int32_t *iters_out, uint8_t *converged_out,
                    int8_t *status_out, void *stream)
 {
-    if (ybus_batched != 0) { set_error("per-instance Ybus values are not supported"); return PF_EINVAL; }
+    if (ybus_batched != 0 && ybus_batched != 1) { set_error("ybus_batched must be 0 or 1"); return PF_EINVAL; }
     return run(plan, batch, ybus, sbus, v0, tol, max_iter, opts, workspace, workspace_bytes, MODE_SOLVE,
-               v_out, iters_out, converged_out, status_out, nullptr, nullptr, stream);
+               v_out, iters_out, converged_out, status_out, nullptr, nullptr, stream, nullptr, ybus_batched);
 }
 
 int pf_solve_batch_warm(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus_batched,
@@ -1330,10 +1294,10 @@ int pf_solve_batch_warm(pf_plan plan, int32_t batch, const double *ybus, int32_t
                         size_t workspace_bytes, double *v_out, int32_t *iters_out, uint8_t *converged_out,
                         int8_t *status_out, void *stream)
 {
-    if (ybus_batched != 0) { set_error("per-instance Ybus values are not supported"); return PF_EINVAL; }
+    if (ybus_batched != 0 && ybus_batched != 1) { set_error("ybus_batched must be 0 or 1"); return PF_EINVAL; }
     if (!v_fallback) { set_error("null fallback start"); return PF_EINVAL; }
     return run(plan, batch, ybus, sbus, v0, tol, max_iter, opts, workspace, workspace_bytes, MODE_SOLVE,
-               v_out, iters_out, converged_out, status_out, nullptr, nullptr, stream, v_fallback);
+               v_out, iters_out, converged_out, status_out, nullptr, nullptr, stream, v_fallback, ybus_batched);
 }
 
 int pf_eval_mismatch(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,

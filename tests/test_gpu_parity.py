@@ -354,3 +354,68 @@ def test_warm_entry_point_restarts_failed_instances(systems):
     torch.cuda.synchronize()
     assert not bool(rn.converged[0:32].any())
     assert bool(ref.converged[0:32].all())
+
+
+@pytest.mark.parametrize("prec", [pf.PF_FP64, pf.PF_FP32_LU])
+def test_n_minus_1_batched_ybus_matches_oracle(systems, prec):
+    """ybus_batched = 1: every instance carries its own Ybus values on the shared pattern
+    (an N-1 contingency: one branch out).  Each instance equals the oracle's solve with
+    that instance's values; FP64 with identical iteration counts."""
+    g, yb, _, plan = systems["c4_100bus"]
+    rng = np.random.default_rng(41)
+    nb = gg.non_bridge_branches(g)
+    B = 77
+    out = rng.choice(nb, size=B)
+    sc = gg.make_scenarios(g, B, 42, "mc")
+    yvals = np.stack([gg.ybus_outage(g, int(k)).val for k in out])
+    r = pf.solve_batch(plan, torch.from_numpy(yvals).to(DEV), torch.from_numpy(sc.sbus).to(DEV),
+                       torch.from_numpy(sc.v0).to(DEV), precision=prec)
+    torch.cuda.synchronize()
+    v = r.v.cpu().numpy(); it = r.iters.cpu().numpy(); cv = r.converged.cpu().numpy().astype(bool)
+    cache = {}
+    for b in range(B):
+        k = int(out[b])
+        if k not in cache:
+            cache[k] = oracle.System.from_ybus(gg.ybus_outage(g, k), g.bus_type)
+        o = cache[k].solve(sc.sbus[b:b + 1], sc.v0[b:b + 1])
+        assert cv[b] == bool(o.converged[0]), b
+        if o.converged[0]:
+            assert np.abs(v[b] - o.v[0]).max() <= 1e-6, b
+            if prec == pf.PF_FP64:
+                assert it[b] == o.iters[0], b
+    assert cv.mean() > 0.9
+
+
+@pytest.mark.parametrize("name", ["c4_100bus", "c1_1350bus"])
+def test_branch_flows_match_oracle(systems, name):
+    """pf_branch_flows at the oracle's solutions: every branch end's S equals the oracle's
+    within 1e-12 (relative to max(1, |S|)); the loss output equals the sum over branches and
+    the total injection sum_i V_i conj((Y V)_i) (power balance); an out-of-range bus index
+    yields NaN for that branch only."""
+    g, yb, osys, _ = systems[name]
+    B = 24
+    sc = gg.make_scenarios(g, B, 51, "mc")
+    o = osys.solve(sc.sbus, sc.v0)
+    ok = o.converged.astype(bool)
+    v = torch.from_numpy(np.ascontiguousarray(o.v)).to(DEV)
+    dv = lambda a, dt=np.float64: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(DEV)
+    f = dv(g.f, np.int32)
+    sf, st, loss = pf.branch_flows(f, dv(g.t, np.int32), dv(g.r), dv(g.x), dv(g.b), g.n, v)
+    torch.cuda.synchronize()
+    sf = sf.cpu().numpy(); st = st.cpu().numpy(); loss = loss.cpu().numpy()
+    Y = np.zeros((g.n, g.n), complex)
+    for i in range(g.n):
+        Y[i, yb.col_idx[yb.row_ptr[i]:yb.row_ptr[i + 1]]] = yb.val[yb.row_ptr[i]:yb.row_ptr[i + 1]]
+    for b in np.flatnonzero(ok):
+        rf, rt = oracle.branch_flows(g, o.v[b])
+        assert np.all(np.abs(sf[b] - rf) <= 1e-12 * np.maximum(1.0, np.abs(rf)))
+        assert np.all(np.abs(st[b] - rt) <= 1e-12 * np.maximum(1.0, np.abs(rt)))
+        assert abs(loss[b] - (sf[b] + st[b]).sum()) <= 1e-12 * max(1.0, np.abs(sf[b]).sum())
+        V = o.v[b, :, 0] * np.exp(1j * o.v[b, :, 1])
+        inj = (V * np.conj(Y @ V)).sum()
+        assert abs(loss[b] - inj) <= 1e-9
+    bad = f.clone()
+    bad[3] = g.n + 5
+    sf2, _, _ = pf.branch_flows(bad, dv(g.t, np.int32), dv(g.r), dv(g.x), dv(g.b), g.n, v[:2])
+    sf2 = sf2.cpu().numpy()
+    assert np.isnan(sf2[:, 3]).all() and np.isfinite(np.delete(sf2, 3, axis=1)).all()

@@ -78,3 +78,44 @@ def test_stress_factor_choice(name, count):
     sc = gg.make_scenarios(g, count, 424242, kind)
     r = s.solve(sc.sbus, sc.v0, threads=8)
     assert r.converged.mean() >= 0.99 - 1.0 / count
+
+
+def test_outage_ybus_keeps_pattern_and_matches_reduced_grid():
+    g = gg.grid("c4_100bus")
+    full = gg.ybus(g)
+    nb = gg.non_bridge_branches(g)
+    assert 0 < nb.size < g.f.size              # the spanning tree's branches are bridges
+    for k in nb[:5]:
+        yk = gg.ybus_outage(g, int(k))
+        assert np.array_equal(yk.row_ptr, full.row_ptr) and np.array_equal(yk.col_idx, full.col_idx)
+        # the outaged branch's two off-diagonal entries are explicit zeros
+        f, t = int(g.f[k]), int(g.t[k])
+        for i, j in ((f, t), (t, f)):
+            q = full.row_ptr[i] + np.flatnonzero(full.col_idx[full.row_ptr[i]:full.row_ptr[i + 1]] == j)[0]
+            assert yk.val[q] == 0
+        # every other entry equals the full Ybus minus the branch's pi model
+        ys = 1.0 / (g.r[k] + 1j * g.x[k])
+        d = full.val - yk.val
+        dense = np.zeros((g.n, g.n), complex)
+        for i in range(g.n):
+            for q in range(full.row_ptr[i], full.row_ptr[i + 1]):
+                dense[i, full.col_idx[q]] = d[q]
+        expect = np.zeros((g.n, g.n), complex)
+        expect[f, f] = expect[t, t] = ys + 0.5j * g.b[k]
+        expect[f, t] = expect[t, f] = -ys
+        assert np.allclose(dense, expect, atol=1e-12)
+
+
+def test_outage_solution_equals_reduced_grid_solution():
+    # the explicit zeros do not change the oracle's power flow: solving on the full pattern
+    # with the outage values equals solving the grid rebuilt without the branch
+    g = gg.grid("c4_100bus")
+    k = int(gg.non_bridge_branches(g)[3])
+    keep = np.ones(g.f.size, bool)
+    keep[k] = False
+    sub = gg.Grid(**{**g.__dict__, "f": g.f[keep], "t": g.t[keep], "r": g.r[keep], "x": g.x[keep], "b": g.b[keep]})
+    sc = gg.make_scenarios(g, 4, 17, "mc")
+    a = oracle.System.from_ybus(gg.ybus_outage(g, k), g.bus_type).solve(sc.sbus, sc.v0)
+    b = oracle.System.from_ybus(gg.ybus(sub), g.bus_type).solve(sc.sbus, sc.v0)
+    assert np.array_equal(a.converged, b.converged) and np.array_equal(a.iters, b.iters)
+    assert np.abs(a.v - b.v).max() <= 1e-10
