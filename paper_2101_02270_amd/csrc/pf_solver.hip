@@ -310,11 +310,39 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         // level order, round-robin over the wavefronts.  The order is topological, so the
         // earliest unfinished panel always has every source published and some wavefront
         // always makes progress; level order keeps independent panels side by side.
+        // The loads of a panel's Jacobian values and right-hand sides do not depend on any
+        // other panel (only the panel itself rewrites its columns and rows), so they are
+        // software-pipelined: while a wavefront works on one panel, the loads of its next
+        // panel are in flight.  A_ROWS rows per lane travel this way; longer panels load
+        // their remaining rows when they start.
+        const LuPanel *lud = P.lu_desc + (size_t)a.sched * P.n_panels;
+        R pa0[A_ROWS], pa1[A_ROWS], py0 = 0, py1 = 0;
+        unsigned char pf[A_ROWS];
+        auto prefetch = [&](const LuPanel &d) {
+            const int jn = d.j2 & ((1 << 30) - 1);
+            const bool tw = (d.j2 >> 30) & 1;
+#pragma unroll
+            for (int r = 0; r < A_ROWS; r++) {
+                const int e = min(s + r * SL, d.cnt - 1);      // rows past the end re-read the last
+                pf[r] = P.isj[d.cs + e];
+                pa0[r] = LU[(size_t)(d.cs + e) * T + t];
+                pa1[r] = LU[(size_t)(d.cs + (tw ? d.cnt : 0) + e) * T + t];
+            }
+            py0 = Yv[jn * T + t];
+            py1 = Yv[(jn + (tw ? 1 : 0)) * T + t];
+        };
+        LuPanel pdn{};
+        if (wave < P.n_panels) {
+            pdn = lud[wave];
+            prefetch(pdn);
+        }
         for (int q = wave; q < P.n_panels; q += NW) {
-            const LuPanel pd = P.lu_desc[(size_t)a.sched * P.n_panels + q];
+            const LuPanel pd = pdn;
             const int j = pd.j2 & ((1 << 30) - 1);
             const bool two = (pd.j2 >> 30) & 1;
             const int cs = pd.cs, cnt = pd.cnt, dr = pd.dr;
+            const bool more = q + NW < P.n_panels;
+            if (more) pdn = lud[q + NW];
             R *xw, *xw1;
             {
                 const SlotRef ls{pd.slot, pd.wait};
@@ -331,27 +359,19 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             }
             // the panel's Jacobian values (written by the mismatch pass; fill positions read
             // as zero; both columns of a pair share the row list and the fill pattern) and
-            // right-hand sides.  Every load of the first A_ROWS rows per lane is issued before
-            // any is used, so they cost one memory round trip together.
+            // right-hand sides
             {
-                R a0[A_ROWS], a1[A_ROWS];
-                unsigned char f[A_ROWS];
-#pragma unroll
-                for (int r = 0; r < A_ROWS; r++) {
-                    const int e = min(s + r * SL, cnt - 1);      // rows past the end re-read the last
-                    f[r] = P.isj[cs + e];
-                    a0[r] = LU[(size_t)(cs + e) * T + t];
-                    a1[r] = LU[(size_t)(cs + (two ? cnt : 0) + e) * T + t];
-                }
-                const R y0 = Yv[j * T + t];
-                const R y1 = Yv[(j + (two ? 1 : 0)) * T + t];
 #pragma unroll
                 for (int r = 0; r < A_ROWS; r++) {
                     const int e = s + r * SL;
                     if (e < cnt) {
-                        xw[e * T + t] = f[r] ? a0[r] : (R)0;
-                        if (two) xw1[e * T + t] = f[r] ? a1[r] : (R)0;
+                        xw[e * T + t] = pf[r] ? pa0[r] : (R)0;
+                        if (two) xw1[e * T + t] = pf[r] ? pa1[r] : (R)0;
                     }
+                }
+                if (s == 0) {
+                    ysl[t] = py0;
+                    if (two) ysl1[t] = py1;
                 }
                 for (int e = s + A_ROWS * SL; e < cnt; e += SL) {
                     const bool fe = P.isj[cs + e];
@@ -360,11 +380,8 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                     xw[e * T + t] = fe ? v0 : (R)0;
                     if (two) xw1[e * T + t] = fe ? v1 : (R)0;
                 }
-                if (s == 0) {
-                    ysl[t] = y0;
-                    if (two) ysl1[t] = y1;
-                }
             }
+            if (more) prefetch(pdn);
             // Updates in ascending source order.  After waiting for the first pending source,
             // the run of following updates whose sources are already published (up to
             // UPD_GROUP) has its operand loads issued together, then the updates are applied
