@@ -47,7 +47,7 @@ void set_error(const std::string &msg) { g_err = msg; }
 
 enum Mode { MODE_SOLVE = 0, MODE_MISMATCH = 1, MODE_FACTOR = 2, MODE_STEP = 3 };
 
-constexpr int UPD_GROUP = 4;     // column updates whose operand loads are issued together
+constexpr int UPD_GROUP = 2;     // column updates whose operand loads are issued together
 
 struct KArgs {
     DevPlan p;
@@ -315,10 +315,33 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         // software-pipelined: while a wavefront works on one panel, the loads of its next
         // panel are in flight.  A_ROWS rows per lane travel this way; longer panels load
         // their remaining rows when they start.
+        //
+        // Metadata travels in vector registers instead of scalar loads (a scalar load is
+        // counted together with LDS operations, so every LDS wait would also wait for it):
+        // one load brings the descriptors of the wavefront's next 8 panels (lane l holds
+        // word l % 8 of descriptor l / 8) and one load the first 16 update records of a
+        // panel (lane l holds word l % 4 of record l / 4); fields are read with readlane.
         const LuPanel *lud = P.lu_desc + (size_t)a.sched * P.n_panels;
+        auto desc_chunk = [&](int c) -> int {
+            const int qq = wave + NW * (8 * c + (lane >> 3));
+            return qq < P.n_panels ? reinterpret_cast<const int *>(lud)[(size_t)qq * 8 + (lane & 7)] : 0;
+        };
+        auto desc_from = [&](int chunk, int k) -> LuPanel {
+            LuPanel d;
+            int *w = reinterpret_cast<int *>(&d);
+#pragma unroll
+            for (int f = 0; f < 8; f++) w[f] = __builtin_amdgcn_readlane(chunk, k * 8 + f);
+            return d;
+        };
+        auto upd_chunk = [&](const LuPanel &d) -> int {
+            const int nu = min(16, d.u1 - d.u0);
+            return lane < 4 * nu ? reinterpret_cast<const int *>(P.upd)[(size_t)d.u0 * 4 + lane] : 0;
+        };
         R pa0[A_ROWS], pa1[A_ROWS], py0 = 0, py1 = 0;
         unsigned char pf[A_ROWS];
+        int pupd = 0;
         auto prefetch = [&](const LuPanel &d) {
+            pupd = upd_chunk(d);
             const int jn = d.j2 & ((1 << 30) - 1);
             const bool tw = (d.j2 >> 30) & 1;
 #pragma unroll
@@ -331,18 +354,21 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             py0 = Yv[jn * T + t];
             py1 = Yv[(jn + (tw ? 1 : 0)) * T + t];
         };
-        LuPanel pdn{};
-        if (wave < P.n_panels) {
-            pdn = lud[wave];
-            prefetch(pdn);
-        }
-        for (int q = wave; q < P.n_panels; q += NW) {
-            const LuPanel pd = pdn;
+        int dch0 = desc_chunk(0), dch1 = desc_chunk(1);
+        if (wave < P.n_panels) prefetch(desc_from(dch0, 0));
+        for (int q = wave, qi = 0; q < P.n_panels; q += NW, qi++) {
+            const int kq = qi & 7;
+            const LuPanel pd = desc_from(dch0, kq);
+            const int ucur = pupd;
             const int j = pd.j2 & ((1 << 30) - 1);
             const bool two = (pd.j2 >> 30) & 1;
             const int cs = pd.cs, cnt = pd.cnt, dr = pd.dr;
             const bool more = q + NW < P.n_panels;
-            if (more) pdn = lud[q + NW];
+            const LuPanel pdn = kq < 7 ? desc_from(dch0, kq + 1) : desc_from(dch1, 0);
+            if (kq == 7) {
+                dch0 = dch1;
+                dch1 = desc_chunk((qi >> 3) + 2);
+            }
             R *xw, *xw1;
             {
                 const SlotRef ls{pd.slot, pd.wait};
@@ -387,15 +413,27 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             // UPD_GROUP) has its operand loads issued together, then the updates are applied
             // one after another in LDS (the order of the arithmetic is unchanged).
             const int u0 = pd.u0, u1 = pd.u1;
+            auto upd_rec = [&](int u) -> Update {
+                const int r = u - u0;
+                if (r < 16) {
+                    Update x;
+                    x.krel_lcnt = __builtin_amdgcn_readlane(ucur, 4 * r);
+                    x.lbeg = __builtin_amdgcn_readlane(ucur, 4 * r + 1);
+                    x.roff = __builtin_amdgcn_readlane(ucur, 4 * r + 2);
+                    x.k = __builtin_amdgcn_readlane(ucur, 4 * r + 3);
+                    return x;
+                }
+                return P.upd[u];
+            };
             for (int ub = u0; ub < u1;) {
                 Update ups[UPD_GROUP];
-                ups[0] = P.upd[ub];
+                ups[0] = upd_rec(ub);
                 wait_published(done, ups[0].k, err);
                 int gcnt = 1;
 #pragma unroll
                 for (int g = 1; g < UPD_GROUP; g++) {
                     if (gcnt == g && ub + g < u1) {
-                        ups[g] = P.upd[ub + g];
+                        ups[g] = upd_rec(ub + g);
                         const int f = __builtin_amdgcn_readfirstlane((int)__hip_atomic_load(
                             &done[ups[g].k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
                         if (f) gcnt = g + 1;
@@ -493,8 +531,24 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         // Panels in back-substitution level order.  For a pair (j, j+1) the rows share their
         // column set i > j+1, and U(j, i), U(j+1, i) sit next to each other in column i.
         const bool upd_v = (a.mode == MODE_SOLVE);
-        for (int q = wave; q < P.n_panels; q += NW) {
-            const BsPanel pd = P.bs_desc[(size_t)a.sched * P.n_panels + q];
+        const BsPanel *bsd = P.bs_desc + (size_t)a.sched * P.n_panels;
+        auto bs_chunk = [&](int c) -> int {
+            const int qq = wave + NW * (8 * c + (lane >> 3));
+            return qq < P.n_panels ? reinterpret_cast<const int *>(bsd)[(size_t)qq * 8 + (lane & 7)] : 0;
+        };
+        int bch0 = bs_chunk(0), bch1 = bs_chunk(1);
+        for (int q = wave, qi = 0; q < P.n_panels; q += NW, qi++) {
+            const int kq = qi & 7;
+            BsPanel pd;
+            {
+                int *w = reinterpret_cast<int *>(&pd);
+#pragma unroll
+                for (int f = 0; f < 8; f++) w[f] = __builtin_amdgcn_readlane(bch0, kq * 8 + f);
+            }
+            if (kq == 7) {
+                bch0 = bch1;
+                bch1 = bs_chunk((qi >> 3) + 2);
+            }
             const int j = pd.j2 & ((1 << 30) - 1);
             const bool two = (pd.j2 >> 30) & 1;
             const int cs = pd.cs, dr = pd.dr, cs1 = pd.cs1;
