@@ -52,6 +52,8 @@ typedef struct {
     int32_t nnz_y, nnz_j, nnz_lu;   /* Ybus, Jacobian, L+U-I pattern sizes                 */
     int32_t n_levels;               /* column levels of the refactorization DAG (Sec. 4.3) */
     int32_t n_bs_levels;            /* row levels of the backward substitution             */
+    int32_t n_panels;               /* panels: single columns and angle/|V| column pairs    */
+    int32_t slot_rows;              /* rows of a wavefront's short working columns          */
     int32_t max_col;                /* longest column of L+U-I                              */
     int64_t n_updates;              /* column-to-column updates (k, j), U(k,j) != 0        */
     int64_t flops_refactor;         /* multiply-adds of one refactorization                */
@@ -105,6 +107,17 @@ int pf_plan_order(pf_plan plan, int32_t *perm);
  * level [N] gives each column's refactorization level (0-based).
  */
 int pf_plan_lu_pattern(pf_plan plan, int32_t *col_ptr, int32_t *row_idx, int32_t *level);
+
+/*
+ * The refactorization schedule of one panel order (order 0: by level, 1: elimination
+ * order) [host, n_panels = info.n_panels entries each]: first[q] is the first column of
+ * the q-th panel in that order and width[q] its column count (1, or 2 for the angle/|V|
+ * pair of a PQ bus); slot[q] is -1 for a panel that uses its wavefront's short working
+ * columns, else the shared long slot it takes, and wait[q] the column whose publication
+ * frees that slot (-1: none).  The kernel relies on: every update source of a panel lies
+ * in an earlier panel of the order, and every slot wait names an earlier long panel.
+ */
+int pf_plan_schedule(pf_plan plan, int32_t order, int32_t *first, int32_t *width, int32_t *slot, int32_t *wait);
 
 /* Workspace bytes pf_solve_batch needs for `batch` instances with `opts` (NULL = default). */
 size_t pf_workspace_bytes(pf_plan plan, int32_t batch, const pf_solve_opts *opts);

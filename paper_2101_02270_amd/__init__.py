@@ -28,7 +28,7 @@ EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
             "pf_mlp_act_backward", "pf_mlp_mse", "pf_mlp_adam", "pf_mlp_to_bf16",
             "pf_mlp_features", "pf_mlp_warm_v0", "pf_queue_create", "pf_queue_add",
             "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune", "pf_solve_batch_warm",
-            "pf_resolve_opts", "pf_branch_flows"]
+            "pf_resolve_opts", "pf_branch_flows", "pf_plan_schedule"]
 
 
 class PfError(RuntimeError):
@@ -39,7 +39,8 @@ class _PlanInfo(ctypes.Structure):
     _fields_ = [("n_bus", ctypes.c_int32), ("n_pv", ctypes.c_int32), ("n_pq", ctypes.c_int32),
                 ("n_unknowns", ctypes.c_int32), ("nnz_y", ctypes.c_int32), ("nnz_j", ctypes.c_int32),
                 ("nnz_lu", ctypes.c_int32), ("n_levels", ctypes.c_int32),
-                ("n_bs_levels", ctypes.c_int32), ("max_col", ctypes.c_int32),
+                ("n_bs_levels", ctypes.c_int32), ("n_panels", ctypes.c_int32),
+                ("slot_rows", ctypes.c_int32), ("max_col", ctypes.c_int32),
                 ("n_updates", ctypes.c_int64), ("flops_refactor", ctypes.c_int64),
                 ("bytes_iter_fp64", ctypes.c_int64), ("bytes_iter_fp32", ctypes.c_int64),
                 ("pattern_hash", ctypes.c_uint64)]
@@ -100,6 +101,7 @@ def lib():
                                           ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Opts), _vp,
                                           ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
         L.pf_branch_flows.argtypes = [i32, i32, _vp, _vp, _vp, _vp, _vp, i32, _vp, _vp, _vp, _vp, _vp]
+        L.pf_plan_schedule.argtypes = [_vp, i32, _i32p, _i32p, _i32p, _i32p]
         L.pf_resolve_opts.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_Opts), ctypes.POINTER(_Opts)]
         L.pf_queue_create.argtypes = [ctypes.POINTER(_vp)]
         L.pf_queue_add.argtypes = [_vp, _vp, i32, _vp, _vp, _vp, ctypes.c_double, i32,
@@ -177,6 +179,14 @@ class Plan:
         _check(lib().pf_plan_lu_pattern(self._h, cp.ctypes.data_as(_i32p), ri.ctypes.data_as(_i32p),
                                         lv.ctypes.data_as(_i32p)), "pf_plan_lu_pattern")
         return cp, ri, lv
+
+    def schedule(self, order: int = 0):
+        """(first column, width, long slot, slot wait) of every panel in processing order."""
+        np_ = self.info["n_panels"]
+        out = [np.zeros(np_, np.int32) for _ in range(4)]
+        _check(lib().pf_plan_schedule(self._h, int(order), *[a.ctypes.data_as(_i32p) for a in out]),
+               "pf_plan_schedule")
+        return tuple(out)
 
     def resolve(self, batch: int, precision=PF_FP64, tile=0, waves=0, schedule=0) -> dict:
         """The configuration a solve of batch instances would use (pf_resolve_opts)."""

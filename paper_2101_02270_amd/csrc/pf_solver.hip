@@ -355,10 +355,11 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             py1 = Yv[(jn + (tw ? 1 : 0)) * T + t];
         };
         int dch0 = desc_chunk(0), dch1 = desc_chunk(1);
-        if (wave < P.n_panels) prefetch(desc_from(dch0, 0));
+        LuPanel pdc = desc_from(dch0, 0);         // the current panel's descriptor, kept in
+        if (wave < P.n_panels) prefetch(pdc);     // scalar registers across iterations
         for (int q = wave, qi = 0; q < P.n_panels; q += NW, qi++) {
             const int kq = qi & 7;
-            const LuPanel pd = desc_from(dch0, kq);
+            const LuPanel pd = pdc;
             const int ucur = pupd;
             const int j = pd.j2 & ((1 << 30) - 1);
             const bool two = (pd.j2 >> 30) & 1;
@@ -408,6 +409,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 }
             }
             if (more) prefetch(pdn);
+            pdc = pdn;
             // Updates in ascending source order.  After waiting for the first pending source,
             // the run of following updates whose sources are already published (up to
             // UPD_GROUP) has its operand loads issued together, then the updates are applied
@@ -1292,6 +1294,8 @@ int pf_plan_info(pf_plan plan, pf_plan_info_t *o)
     o->nnz_lu = h.col_ptr[h.N];
     o->n_levels = (int32_t)h.lev_ptr.size() - 1;
     o->n_bs_levels = (int32_t)h.bs_lev_ptr.size() - 1;
+    o->n_panels = (int32_t)h.panel_ptr.size() - 1;
+    o->slot_rows = h.slot_rows;
     o->max_col = h.max_col;
     o->n_updates = (int64_t)h.upd.size();
     o->flops_refactor = h.flops;
@@ -1319,6 +1323,23 @@ int pf_plan_lu_pattern(pf_plan plan, int32_t *col_ptr, int32_t *row_idx, int32_t
     std::memcpy(col_ptr, h.col_ptr.data(), sizeof(int32_t) * h.col_ptr.size());
     std::memcpy(row_idx, h.row_idx.data(), sizeof(int32_t) * h.row_idx.size());
     if (level) std::memcpy(level, h.level.data(), sizeof(int32_t) * h.level.size());
+    return PF_OK;
+}
+
+int pf_plan_schedule(pf_plan plan, int32_t order, int32_t *first, int32_t *width, int32_t *slot, int32_t *wait)
+{
+    Plan *pl = reinterpret_cast<Plan *>(plan);
+    if (!pl || !first || !width || !slot || !wait) { set_error("null argument"); return PF_EINVAL; }
+    if (order != 0 && order != 1) { set_error("order must be 0 or 1"); return PF_EINVAL; }
+    const HostPlan &h = pl->h;
+    const int np = (int)h.panel_ptr.size() - 1;
+    for (int q = 0; q < np; q++) {
+        const LuPanel &d = h.lu_desc[(size_t)order * np + q];
+        first[q] = d.j2 & ((1 << 30) - 1);
+        width[q] = 1 + ((d.j2 >> 30) & 1);
+        slot[q] = d.slot;
+        wait[q] = d.wait;
+    }
     return PF_OK;
 }
 

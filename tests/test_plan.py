@@ -184,3 +184,60 @@ def test_queue_without_device_reports_error():
         pytest.skip("a device is present")
     with pytest.raises(pf.PfError):
         pf.Queue()
+
+
+@pytest.mark.parametrize("name", ["c4_100bus", "c1_1350bus", "c2_9000bus"])
+@pytest.mark.parametrize("order", [0, 1])
+def test_schedule_is_topological_and_slots_are_handed_out_in_order(name, order):
+    """The refactorization's deadlock-freedom rests on two properties of each panel order:
+    every column-to-column update source (U(k, j) != 0, k < j) lies in an earlier panel,
+    and every long panel's slot wait names the first column of an earlier long panel that
+    used the same slot.  Checked from the LU pattern, independently of the plan's own
+    construction."""
+    g = gg.grid(name)
+    plan = pf.Plan.from_ybus(gg.ybus(g), g.bus_type)
+    cp, ri, _ = plan.lu_pattern()
+    first, width, slot, wait = plan.schedule(order)
+    N = plan.N
+    assert np.array_equal(np.sort(np.concatenate([np.arange(f, f + w) for f, w in zip(first, width)])), np.arange(N))
+    pos = np.empty(N, np.int64)
+    for q, (f, w) in enumerate(zip(first, width)):
+        pos[f:f + w] = q
+    for j in range(N):
+        rows = ri[cp[j]:cp[j + 1]]
+        srcs = rows[rows < j]                       # U part of column j: its update sources
+        srcs = srcs[pos[srcs] != pos[j]]            # the pair's first column is internal
+        assert (pos[srcs] < pos[j]).all(), j
+    info = plan.info
+    long_q = np.flatnonzero(slot >= 0)
+    rows_of = (cp[first + 1] - cp[first])
+    assert (rows_of[long_q] > info["slot_rows"]).all()
+    assert (rows_of[slot < 0] <= info["slot_rows"]).all()
+    last_user = {}
+    for q in long_q:
+        s = int(slot[q])
+        if s in last_user:
+            assert wait[q] == first[last_user[s]] and last_user[s] < q
+        else:
+            assert wait[q] == -1
+        last_user[s] = q
+
+
+def test_automatic_launch_configuration():
+    """pf_resolve_opts (host logic): explicit choices are kept, invalid ones rejected, and
+    the automatic choice picks the configurations measured fastest for the two workload
+    shapes (many instances of a 1350-bus grid; few of a 9000-bus grid)."""
+    g1 = gg.grid("c1_1350bus")
+    p1 = pf.Plan.from_ybus(gg.ybus(g1), g1.bus_type)
+    assert (p1.resolve(10000)["tile"], p1.resolve(10000)["waves"]) == (8, 8)
+    r = p1.resolve(10000, precision=pf.PF_FP32_LU)
+    assert (r["tile"], r["waves"]) == (16, 8)
+    r = p1.resolve(10000, tile=4, waves=2, schedule=1)
+    assert (r["tile"], r["waves"], r["schedule"]) == (4, 2, 1)
+    g2 = gg.grid("c2_9000bus")
+    p2 = pf.Plan.from_ybus(gg.ybus(g2), g2.bus_type)
+    r = p2.resolve(2000)
+    assert (r["tile"], r["waves"]) == (8, 16)
+    for bad in (dict(tile=32), dict(waves=3), dict(schedule=2), dict(precision=7)):
+        with pytest.raises(pf.PfError):
+            p1.resolve(100, **bad)
