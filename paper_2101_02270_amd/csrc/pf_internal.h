@@ -102,20 +102,16 @@ struct HostPlan {
     int64_t flops = 0;
 };
 
-// Device copy of the plan: one allocation, pointers into it.
+// Device copy of what the kernels read of the plan: one allocation, pointers into it.
 struct DevPlan {
-    int n, nnzy, N, nnzlu, n_levels, n_bs_levels, max_col, npvpq;
-    const int32_t *yrp, *yci, *yrow;
-    const int8_t *bus_type;
-    const int32_t *col_ptr, *col_diag;
+    int n, nnzy, N, nnzlu, max_col;
+    const int32_t *yrp, *yci;
     const JPos *jpos;
     const uint8_t *isj;
-    const int32_t *upd_ptr, *rel;
+    const int32_t *rel;
     const Update *upd;
-    const int32_t *lev_ptr, *lev_cols, *bs_lev_ptr, *bs_lev_rows;
-    const int32_t *bs_ptr, *bs_pos, *bs_col;
-    const int32_t *bus_peq, *bus_qeq, *pos_upd;
-    const int32_t *panel_ptr, *lu_seq, *bs_seq;
+    const int32_t *bs_pos, *bs_col;
+    const int32_t *bus_peq, *bus_qeq;
     const LuPanel *lu_desc;
     const BsPanel *bs_desc;
     int n_panels, slot_rows, n_long;

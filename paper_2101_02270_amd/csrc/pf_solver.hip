@@ -942,27 +942,20 @@ static int upload(Plan *pl)
     const HostPlan &h = pl->h;
     if (hipGetDevice(&pl->device) != hipSuccess) { set_error("no HIP device"); return PF_EDEVICE; }
     DevOffsets off;
-    const size_t o_yrp = off.add(h.yrp), o_yci = off.add(h.yci), o_yrow = off.add(h.yrow);
-    const size_t o_bt = off.add(h.bus_type), o_cp = off.add(h.col_ptr), o_cd = off.add(h.col_diag);
-    const size_t o_jpos = off.add(h.jpos), o_isj = off.add(h.isj), o_up = off.add(h.upd_ptr), o_rel = off.add(h.rel);
-    const size_t o_upd = off.add(h.upd), o_lp = off.add(h.lev_ptr);
-    const size_t o_lc = off.add(h.lev_cols), o_blp = off.add(h.bs_lev_ptr), o_blr = off.add(h.bs_lev_rows);
-    const size_t o_bp = off.add(h.bs_ptr), o_bpos = off.add(h.bs_pos), o_bcol = off.add(h.bs_col);
-    const size_t o_pe = off.add(h.bus_peq), o_qe = off.add(h.bus_qeq), o_pu = off.add(h.pos_upd);
-    const size_t o_perm = off.add(h.perm), o_pp = off.add(h.panel_ptr);
-    const size_t o_ls = off.add(h.lu_seq), o_bsq = off.add(h.bs_seq);
+    const size_t o_yrp = off.add(h.yrp), o_yci = off.add(h.yci);
+    const size_t o_jpos = off.add(h.jpos), o_isj = off.add(h.isj), o_rel = off.add(h.rel);
+    const size_t o_upd = off.add(h.upd);
+    const size_t o_bpos = off.add(h.bs_pos), o_bcol = off.add(h.bs_col);
+    const size_t o_pe = off.add(h.bus_peq), o_qe = off.add(h.bus_qeq);
+    const size_t o_perm = off.add(h.perm);
     const size_t o_lud = off.add(h.lu_desc), o_bsd = off.add(h.bs_desc);
     std::vector<char> host(off.bytes, 0);
     auto put = [&](size_t o, const auto &v) {
         if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * sizeof(v[0]));
     };
-    put(o_yrp, h.yrp); put(o_yci, h.yci); put(o_yrow, h.yrow); put(o_bt, h.bus_type);
-    put(o_cp, h.col_ptr); put(o_cd, h.col_diag); put(o_jpos, h.jpos); put(o_isj, h.isj); put(o_up, h.upd_ptr);
-    put(o_rel, h.rel); put(o_upd, h.upd); put(o_lp, h.lev_ptr);
-    put(o_lc, h.lev_cols); put(o_blp, h.bs_lev_ptr); put(o_blr, h.bs_lev_rows); put(o_bp, h.bs_ptr);
-    put(o_bpos, h.bs_pos); put(o_bcol, h.bs_col); put(o_pe, h.bus_peq); put(o_qe, h.bus_qeq);
-    put(o_pu, h.pos_upd); put(o_perm, h.perm); put(o_pp, h.panel_ptr);
-    put(o_ls, h.lu_seq); put(o_bsq, h.bs_seq); put(o_lud, h.lu_desc); put(o_bsd, h.bs_desc);
+    put(o_yrp, h.yrp); put(o_yci, h.yci); put(o_jpos, h.jpos); put(o_isj, h.isj); put(o_rel, h.rel);
+    put(o_upd, h.upd); put(o_bpos, h.bs_pos); put(o_bcol, h.bs_col); put(o_pe, h.bus_peq);
+    put(o_qe, h.bus_qeq); put(o_perm, h.perm); put(o_lud, h.lu_desc); put(o_bsd, h.bs_desc);
     void *dm = nullptr;
     if (hipMalloc(&dm, off.bytes) != hipSuccess) { set_error("hipMalloc of the plan failed"); return PF_ENOMEM; }
     if (hipMemcpy(dm, host.data(), off.bytes, hipMemcpyHostToDevice) != hipSuccess) {
@@ -974,22 +967,13 @@ static int upload(Plan *pl)
     pl->dev_bytes = off.bytes;
     const char *D = reinterpret_cast<const char *>(dm);
     DevPlan &d = pl->d;
-    d.n = h.n; d.nnzy = h.nnzy; d.N = h.N; d.nnzlu = h.col_ptr[h.N];
-    d.n_levels = (int)h.lev_ptr.size() - 1; d.n_bs_levels = (int)h.bs_lev_ptr.size() - 1;
-    d.max_col = h.max_col; d.npvpq = h.npvpq;
-    d.yrp = (const int32_t *)(D + o_yrp); d.yci = (const int32_t *)(D + o_yci); d.yrow = (const int32_t *)(D + o_yrow);
-    d.bus_type = (const int8_t *)(D + o_bt);
-    d.col_ptr = (const int32_t *)(D + o_cp); d.col_diag = (const int32_t *)(D + o_cd); d.jpos = (const JPos *)(D + o_jpos); d.isj = (const uint8_t *)(D + o_isj);
-    d.upd_ptr = (const int32_t *)(D + o_up); d.rel = (const int32_t *)(D + o_rel);
-    d.upd = (const Update *)(D + o_upd);
-    d.lev_ptr = (const int32_t *)(D + o_lp); d.lev_cols = (const int32_t *)(D + o_lc);
-    d.bs_lev_ptr = (const int32_t *)(D + o_blp); d.bs_lev_rows = (const int32_t *)(D + o_blr);
-    d.bs_ptr = (const int32_t *)(D + o_bp); d.bs_pos = (const int32_t *)(D + o_bpos); d.bs_col = (const int32_t *)(D + o_bcol);
-    d.bus_peq = (const int32_t *)(D + o_pe); d.bus_qeq = (const int32_t *)(D + o_qe); d.pos_upd = (const int32_t *)(D + o_pu);
+    d.n = h.n; d.nnzy = h.nnzy; d.N = h.N; d.nnzlu = h.col_ptr[h.N]; d.max_col = h.max_col;
+    d.yrp = (const int32_t *)(D + o_yrp); d.yci = (const int32_t *)(D + o_yci);
+    d.jpos = (const JPos *)(D + o_jpos); d.isj = (const uint8_t *)(D + o_isj);
+    d.rel = (const int32_t *)(D + o_rel); d.upd = (const Update *)(D + o_upd);
+    d.bs_pos = (const int32_t *)(D + o_bpos); d.bs_col = (const int32_t *)(D + o_bcol);
+    d.bus_peq = (const int32_t *)(D + o_pe); d.bus_qeq = (const int32_t *)(D + o_qe);
     pl->perm_dev = (const int32_t *)(D + o_perm);
-    d.panel_ptr = (const int32_t *)(D + o_pp);
-    d.lu_seq = (const int32_t *)(D + o_ls);
-    d.bs_seq = (const int32_t *)(D + o_bsq);
     d.lu_desc = (const LuPanel *)(D + o_lud);
     d.bs_desc = (const BsPanel *)(D + o_bsd);
     d.n_panels = (int)h.panel_ptr.size() - 1;
