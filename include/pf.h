@@ -301,6 +301,22 @@ int pf_branch_flows(int32_t n_bus, int32_t n_branch, const int32_t *from_bus, co
                     const double *r, const double *x, const double *b_total, int32_t batch, const double *v,
                     double *s_from, double *s_to, double *loss, void *stream);
 
+/*
+ * pf_solve_host: pf_solve_batch for a batch that lives in host memory.  The batch is
+ * solved in chunks of `chunk` instances on two internal streams, so that one chunk's
+ * copies overlap the other's solve; all chunks use the configuration pf_resolve_opts gives
+ * for `chunk` instances.  ybus [device] as in pf_solve_batch (shared values); sbus_host,
+ * v0_host [host, batch x n_bus x 2] in; v_out_host [host, same shape], iters_host,
+ * converged_host, status_host (may be NULL) [host, batch] out.  Host buffers should be
+ * pinned (hipHostMalloc) for the copies to overlap; pageable memory works but copies
+ * synchronously.  The work starts after what is already queued on stream; the call
+ * returns when every result is in host memory.  Allocates and frees its own device
+ * buffers and streams (default priority).
+ */
+int pf_solve_host(pf_plan plan, int32_t batch, const double *ybus, const double *sbus_host, const double *v0_host,
+                  double tol, int32_t max_iter, const pf_solve_opts *opts, int32_t chunk, double *v_out_host,
+                  int32_t *iters_host, uint8_t *converged_host, int8_t *status_host, void *stream);
+
 /* Release the plan and its device memory. */
 void pf_plan_destroy(pf_plan plan);
 

@@ -28,7 +28,7 @@ EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
             "pf_mlp_act_backward", "pf_mlp_mse", "pf_mlp_adam", "pf_mlp_to_bf16",
             "pf_mlp_features", "pf_mlp_warm_v0", "pf_queue_create", "pf_queue_add",
             "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune", "pf_solve_batch_warm",
-            "pf_resolve_opts", "pf_branch_flows", "pf_plan_schedule"]
+            "pf_resolve_opts", "pf_branch_flows", "pf_plan_schedule", "pf_solve_host"]
 
 
 class PfError(RuntimeError):
@@ -101,6 +101,8 @@ def lib():
                                           ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Opts), _vp,
                                           ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
         L.pf_branch_flows.argtypes = [i32, i32, _vp, _vp, _vp, _vp, _vp, i32, _vp, _vp, _vp, _vp, _vp]
+        L.pf_solve_host.argtypes = [_vp, i32, _vp, _vp, _vp, ctypes.c_double, i32, ctypes.POINTER(_Opts), i32,
+                                    _vp, _vp, _vp, _vp, _vp]
         L.pf_plan_schedule.argtypes = [_vp, i32, _i32p, _i32p, _i32p, _i32p]
         L.pf_resolve_opts.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_Opts), ctypes.POINTER(_Opts)]
         L.pf_queue_create.argtypes = [ctypes.POINTER(_vp)]
@@ -441,3 +443,27 @@ def branch_flows(from_bus, to_bus, r, x, b_total, n_bus: int, v, losses: bool = 
     _check(rc, "pf_branch_flows")
     return (torch.view_as_complex(sf), torch.view_as_complex(st),
             torch.view_as_complex(loss) if losses else None)
+
+
+def solve_host(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10, precision: int = PF_FP64,
+               tile: int = 0, waves: int = 0, chunk: int = 2048, stream=None):
+    """pf_solve_host: ybus a device tensor as in solve_batch; sbus complex128 [B][n] and v0
+    float64 [B][n][2] host tensors (pinned for overlap).  Returns a Result of pinned host
+    tensors."""
+    torch = _torch()
+    B = int(v0.shape[0])
+    yp, _, _ = _ybus_view(plan, ybus)
+    s2 = _as_pairs(sbus, "sbus")
+    for t_, nm in ((s2, "sbus"), (v0, "v0")):
+        if t_.is_cuda or t_.dtype != torch.float64 or not t_.is_contiguous() or tuple(t_.shape) != (B, plan.n, 2):
+            raise PfError(f"{nm} must be a contiguous float64 host tensor of shape {(B, plan.n, 2)}")
+    out = Result(v=torch.empty((B, plan.n, 2), dtype=torch.float64, pin_memory=True),
+                 iters=torch.empty(B, dtype=torch.int32, pin_memory=True),
+                 converged=torch.empty(B, dtype=torch.uint8, pin_memory=True),
+                 status=torch.empty(B, dtype=torch.int8, pin_memory=True))
+    rc = lib().pf_solve_host(plan._h, B, yp, _vp(s2.data_ptr()), _vp(v0.data_ptr()), float(tol), int(max_iter),
+                             ctypes.byref(_Opts(precision, tile, waves, 0)), int(chunk), _vp(out.v.data_ptr()),
+                             _vp(out.iters.data_ptr()), _vp(out.converged.data_ptr()), _vp(out.status.data_ptr()),
+                             _stream_ptr(stream))
+    _check(rc, "pf_solve_host")
+    return out

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpf_hip.so")
-SOURCES = ["pf_solver.hip", "pf_plan.cpp", "pf_mlp.hip", "pf_flows.hip"]
+SOURCES = ["pf_solver.hip", "pf_plan.cpp", "pf_mlp.hip", "pf_flows.hip", "pf_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

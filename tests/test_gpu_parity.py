@@ -419,3 +419,20 @@ def test_branch_flows_match_oracle(systems, name):
     sf2, _, _ = pf.branch_flows(bad, dv(g.t, np.int32), dv(g.r), dv(g.x), dv(g.b), g.n, v[:2])
     sf2 = sf2.cpu().numpy()
     assert np.isnan(sf2[:, 3]).all() and np.isfinite(np.delete(sf2, 3, axis=1)).all()
+
+
+def test_host_resident_pipelined_solve_matches_device_solve(systems):
+    """pf_solve_host: a host batch solved in chunks on two streams (ragged last chunk)
+    gives exactly the device-resident results for the same launch configuration."""
+    g, yb, _, plan = systems["c4_100bus"]
+    sc = gg.make_scenarios(g, 1000, 61, "mc")
+    y = torch.from_numpy(yb.val).to(DEV)
+    s_h = torch.view_as_real(torch.from_numpy(sc.sbus)).contiguous().pin_memory()
+    v_h = torch.from_numpy(sc.v0).contiguous().pin_memory()
+    cfg = plan.resolve(300)
+    r = pf.solve_host(plan, y, s_h, v_h, chunk=300, tile=cfg["tile"], waves=cfg["waves"])
+    d = pf.solve_batch(plan, y, s_h.to(DEV), v_h.to(DEV), tile=cfg["tile"], waves=cfg["waves"])
+    torch.cuda.synchronize()
+    assert torch.equal(r.v, d.v.cpu())
+    assert torch.equal(r.iters, d.iters.cpu()) and torch.equal(r.converged, d.converged.cpu())
+    assert torch.equal(r.status, d.status.cpu())
