@@ -169,11 +169,12 @@ int pf_solve_batch(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus
 /*
  * pf_solve_batch_warm: pf_solve_batch from the start v0 (e.g. a learned prediction) with
  * an in-kernel fallback: an instance whose attempt from v0 fails (non-finite mismatch, an
- * update that does not reduce max|F|, max_iter updates without convergence, or a zero
- * pivot) restarts once from v_fallback
- * [device, B x n_bus x 2, same layout as v0; typically the flat start], with a fresh
- * max_iter budget.  iters_out counts the voltage updates of both attempts; status and
- * converged describe the final attempt.  Other arguments and errors as pf_solve_batch.
+ * update that does not reduce max|F|, or a zero pivot) restarts once from v_fallback
+ * [device, B x n_bus x 2, same layout as v0; typically the flat start].  max_iter bounds
+ * the voltage updates of both attempts together, so a restarted instance never runs
+ * longer than a plain solve could; iters_out counts those updates; status and converged
+ * describe the final attempt.
+ * Other arguments and errors as pf_solve_batch.
  */
 int pf_solve_batch_warm(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus_batched,
                         const double *sbus, const double *v0, const double *v_fallback, double tol,

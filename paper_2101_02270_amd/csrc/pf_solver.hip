@@ -118,7 +118,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     __shared__ double s_red[NW][T];
     __shared__ int s_bad[NW][T];
     __shared__ int s_active[T], s_status[T], s_iters[T], s_piv[T];
-    __shared__ int s_retry[T], s_reset[T], s_it0[T], s_nupd[T];
+    __shared__ int s_retry[T], s_reset[T], s_nupd[T];
     __shared__ double s_prevf[T];
     __shared__ double s_normf[T];
     __shared__ int s_any, s_err;
@@ -171,7 +171,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         s_active[t] = valid ? 1 : 0;
         s_status[t] = PF_ST_MAXITER;
         s_iters[t] = 0;
-        s_retry[t] = 0; s_reset[t] = 0; s_it0[t] = 0; s_nupd[t] = 0;
+        s_retry[t] = 0; s_reset[t] = 0; s_nupd[t] = 0;
         s_prevf[t] = INFINITY;
     }
     if (tid == 0) s_err = 0;
@@ -271,17 +271,18 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             s_normf[t] = nb ? NAN : nf;
             s_piv[t] = 0;
             if (s_active[t] && a.mode == MODE_SOLVE) {
-                // iters counts voltage updates over all attempts; max_iter bounds each attempt
+                // iters counts voltage updates; max_iter bounds them over both attempts (a
+                // plain solve updates once per iteration, so this is its iteration bound)
                 int fail = 0;
                 if (nb) fail = PF_ST_NONFINITE;
                 else if (nf < a.tol) { s_status[t] = PF_ST_CONVERGED; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
-                else if (it - s_it0[t] >= a.max_iter) fail = PF_ST_MAXITER;
+                else if (s_nupd[t] >= a.max_iter) fail = PF_ST_MAXITER;
                 // an attempt that has a fallback gives up as soon as an update fails to
                 // reduce the mismatch (Newton from a good start contracts every step)
                 else if (a.v_fb && !s_retry[t] && !(nf < s_prevf[t])) fail = PF_ST_MAXITER;
                 s_prevf[t] = nf;
                 if (fail) {
-                    if (a.v_fb && !s_retry[t]) { s_retry[t] = 1; s_reset[t] = 1; s_it0[t] = it + 1; }
+                    if (a.v_fb && !s_retry[t] && s_nupd[t] < a.max_iter) { s_retry[t] = 1; s_reset[t] = 1; }
                     else { s_status[t] = fail; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
                 }
             }
@@ -516,7 +517,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         }
         __syncthreads();
         if (tid < T && s_piv[t] && s_active[t] && !s_reset[t] && a.mode == MODE_SOLVE) {
-            if (a.v_fb && !s_retry[t]) { s_retry[t] = 1; s_reset[t] = 1; s_it0[t] = it + 1; }
+            if (a.v_fb && !s_retry[t]) { s_retry[t] = 1; s_reset[t] = 1; }
             else { s_status[t] = PF_ST_PIVOT; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
         }
         if (a.mode == MODE_FACTOR) {

@@ -328,9 +328,9 @@ def test_fp32_lu_converges_to_fp64_answer(systems, name, B):
 
 def test_warm_entry_point_restarts_failed_instances(systems):
     """pf_solve_batch_warm: instances whose start is broken (|V| = 0 gives a non-finite
-    mismatch at once; a far-off start exhausts max_iter or diverges) restart from the
-    fallback inside the kernel and end exactly where the plain flat-start solve ends; the
-    other instances are untouched by the fallback."""
+    mismatch at once, before any update) restart from the fallback inside the kernel and
+    end exactly where the plain flat-start solve ends; far-off starts stay within the
+    shared max_iter update budget; the other instances are untouched by the fallback."""
     g, yb, osys, plan = systems["c4_100bus"]
     sc = gg.make_scenarios(g, 96, 31, "mc")
     y, s, vflat = to_dev(yb, sc)
@@ -347,8 +347,11 @@ def test_warm_entry_point_restarts_failed_instances(systems):
             assert torch.equal(r.status[sl], r0.status[sl])
             assert torch.equal(r.v[sl], r0.v[sl]) and torch.equal(r.iters[sl], r0.iters[sl])
         # far-off starts: converged from there (possibly to another power-flow solution) or
-        # restarted from the flat start, so never worse than the flat start alone
-        assert bool((r.converged[32:64] >= r0.converged[32:64]).all())
+        # restarted from the flat start within the shared update budget
+        assert bool((r.iters[32:64] <= 10).all())
+        st = r.status[32:64].cpu().numpy()
+        assert np.isin(st, [pf.PF_ST_CONVERGED, pf.PF_ST_MAXITER, pf.PF_ST_NONFINITE, pf.PF_ST_PIVOT]).all()
+        assert bool(r.converged[32:64].float().mean() >= 0.5)
     # without the fallback the broken starts fail
     rn = pf.solve_batch(plan, y, s, v0)
     torch.cuda.synchronize()
