@@ -1,29 +1,29 @@
-// Batched Newton-Raphson power flow on gfx950: one fused, persistent-per-tile kernel.
+// Batched Newton-Raphson power flow on gfx950: one fused kernel per launch.
 //
 // A workgroup owns a tile of T instances and runs their whole Newton loop (Sec. 3 of
 // the paper) without leaving the kernel:
-//   M   mismatch S = V o conj(Y V) (Eq. 1), F = calculated - specified (Alg. 1), the
-//       per-instance infinity norm by wavefront shuffles and an LDS reduction, and the
-//       convergence / divergence decision;
+//   M   rectangular V, then one pass over every Ybus row: I = Y V, S = V o conj(I)
+//       (Eq. 1), F = calculated - specified (Alg. 1), and from the same Y_ik V_k products
+//       the four Jacobian entries of each Ybus entry (Sec. 3.1.2), written straight into
+//       their positions of the permuted matrix A = P J P^T; the per-instance infinity
+//       norm by wavefront shuffles and an LDS reduction, and the convergence decision;
 //   LU  a sync-free dataflow form of the left-looking refactorization (Sec. 4.2-4.3):
-//       each wavefront takes the next column j of A = P J P^T from a counter, builds its
-//       Jacobian entries straight from V and Ybus into an LDS working column (Sec. 3.1.2,
-//       "direct into permuted form A"), applies the update of every column k with
-//       U(k,j) != 0 in ascending k (the sparse VMAD with direct indexing of Alg. 3) as
-//       soon as k is published, carries the forward substitution of the right-hand side
-//       along (row j of L is read in the same pass), normalises the L part, writes the
-//       column back and publishes it.  This generalises the paper's stage 2 (partial
-//       updates of unfinished columns) to every column: no level barriers remain, and
-//       the serial tail of the factorization pipelines across wavefronts;
-//   BS  backward substitution in the same dataflow style (row j waits for the rows
-//       i > j it reads), one wavefront per row, and the voltage update V <- V - dx for
-//       instances still iterating.
+//       wavefronts take panels (a column, or the angle/|V| column pair of a PQ bus) in a
+//       topological order, round-robin; each loads its Jacobian values into LDS working
+//       columns, applies the update of every column k with U(k,j) != 0 in ascending k as
+//       soon as k is published (the sparse multiply-add of Alg. 3 with direct indexing),
+//       carries the forward substitution of the right-hand side along, normalises the L
+//       part, writes the columns back and publishes them.  This extends the paper's
+//       second stage (partial updates of unfinished columns) to every column: no level
+//       barriers remain and the serial tail pipelines across wavefronts;
+//   BS  backward substitution in the same dataflow style (a row waits for the rows it
+//       reads), and the voltage update V <- V - dx for instances still iterating.
 // Each entry of every per-instance array is stored tile-interleaved: element e of
 // instance t of a tile lives at [e][t], so a wavefront reading entry e for the tile's
 // instances issues one contiguous T * sizeof(real) access (the paper's batched layout,
-// Sec. 3.1, Fig. "CRS sparse matrix ... batched data" d).  Inside a wavefront the
-// 64 lanes are T instances x (64 / T) sub-lanes that split the rows of a column
-// update (the paper's extra VMAD parallelism).
+// Sec. 3.1, at tile granularity).  Inside a wavefront the 64 lanes are T instances x
+// (64 / T) sub-lanes that split the rows of a column (the paper's extra multiply-add
+// parallelism).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
