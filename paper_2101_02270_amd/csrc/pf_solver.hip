@@ -47,7 +47,8 @@ void set_error(const std::string &msg) { g_err = msg; }
 
 enum Mode { MODE_SOLVE = 0, MODE_MISMATCH = 1, MODE_FACTOR = 2, MODE_STEP = 3 };
 
-constexpr int UPD_GROUP = 2;     // column updates whose operand loads are issued together
+constexpr int UPD_GROUP = 3;     // column updates whose operand loads are issued together
+constexpr int L_ROWS = 2;        // rows of each source column per lane loaded with its group
 
 struct KArgs {
     DevPlan p;
@@ -320,8 +321,10 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         // Metadata travels in vector registers instead of scalar loads (a scalar load is
         // counted together with LDS operations, so every LDS wait would also wait for it):
         // one load brings the descriptors of the wavefront's next 8 panels (lane l holds
-        // word l % 8 of descriptor l / 8) and one load the first 16 update records of a
-        // panel (lane l holds word l % 4 of record l / 4); fields are read with readlane.
+        // word l % 8 of descriptor l / 8) and one load 16 update records of a panel (lane l
+        // holds word l % 4 of record l / 4); fields are read with readlane.  A panel's first
+        // 16 records arrive with its prefetch; a panel with more loads each further chunk
+        // one chunk ahead of its use, so no update group waits for its own records.
         const LuPanel *lud = P.lu_desc + (size_t)a.sched * P.n_panels;
         auto desc_chunk = [&](int c) -> int {
             const int qq = wave + NW * (8 * c + (lane >> 3));
@@ -334,10 +337,11 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             for (int f = 0; f < 8; f++) w[f] = __builtin_amdgcn_readlane(chunk, k * 8 + f);
             return d;
         };
-        auto upd_chunk = [&](const LuPanel &d) -> int {
-            const int nu = min(16, d.u1 - d.u0);
-            return lane < 4 * nu ? reinterpret_cast<const int *>(P.upd)[(size_t)d.u0 * 4 + lane] : 0;
+        auto upd_chunk_at = [&](int ua, int ue) -> int {      // records [ua, min(ua + 16, ue))
+            const int nu = min(16, ue - ua);
+            return lane < 4 * nu ? reinterpret_cast<const int *>(P.upd)[(size_t)ua * 4 + lane] : 0;
         };
+        auto upd_chunk = [&](const LuPanel &d) -> int { return upd_chunk_at(d.u0, d.u1); };
         R pa0[A_ROWS], pa1[A_ROWS], py0 = 0, py1 = 0;
         unsigned char pf[A_ROWS];
         int pupd = 0;
@@ -413,29 +417,36 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             pdc = pdn;
             // Updates in ascending source order.  After waiting for the first pending source,
             // the run of following updates whose sources are already published (up to
-            // UPD_GROUP) has its operand loads issued together, then the updates are applied
-            // one after another in LDS (the order of the arithmetic is unchanged).
+            // UPD_GROUP, within one chunk of records) has its operand loads issued together
+            // (L_ROWS rows of each source column per lane), then the updates are applied one
+            // after another in LDS (the order of the arithmetic is unchanged).  Rows beyond
+            // L_ROWS per lane (the long source columns of the dense tail) are loaded two at a
+            // time.
             const int u0 = pd.u0, u1 = pd.u1;
+            int ubase = u0, uc0 = ucur, uc1 = 0;
+            if (u1 - u0 > 16) uc1 = upd_chunk_at(u0 + 16, u1);
             auto upd_rec = [&](int u) -> Update {
-                const int r = u - u0;
-                if (r < 16) {
-                    Update x;
-                    x.krel_lcnt = __builtin_amdgcn_readlane(ucur, 4 * r);
-                    x.lbeg = __builtin_amdgcn_readlane(ucur, 4 * r + 1);
-                    x.roff = __builtin_amdgcn_readlane(ucur, 4 * r + 2);
-                    x.k = __builtin_amdgcn_readlane(ucur, 4 * r + 3);
-                    return x;
-                }
-                return P.upd[u];
+                const int r = u - ubase;
+                Update x;
+                x.krel_lcnt = __builtin_amdgcn_readlane(uc0, 4 * r);
+                x.lbeg = __builtin_amdgcn_readlane(uc0, 4 * r + 1);
+                x.roff = __builtin_amdgcn_readlane(uc0, 4 * r + 2);
+                x.k = __builtin_amdgcn_readlane(uc0, 4 * r + 3);
+                return x;
             };
             for (int ub = u0; ub < u1;) {
+                if (ub - ubase >= 16) {
+                    ubase += 16;
+                    uc0 = uc1;
+                    if (u1 - ubase > 16) uc1 = upd_chunk_at(ubase + 16, u1);
+                }
                 Update ups[UPD_GROUP];
                 ups[0] = upd_rec(ub);
                 wait_published(done, ups[0].k, err);
                 int gcnt = 1;
 #pragma unroll
                 for (int g = 1; g < UPD_GROUP; g++) {
-                    if (gcnt == g && ub + g < u1) {
+                    if (gcnt == g && ub + g < u1 && ub + g - ubase < 16) {
                         ups[g] = upd_rec(ub + g);
                         const int f = __builtin_amdgcn_readfirstlane((int)__hip_atomic_load(
                             &done[ups[g].k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
@@ -443,17 +454,21 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                R lv[UPD_GROUP], yk[UPD_GROUP];
-                int rv[UPD_GROUP];
+                R lv[UPD_GROUP][L_ROWS], yk[UPD_GROUP];
+                int rv[UPD_GROUP][L_ROWS];
 #pragma unroll
                 for (int g = 0; g < UPD_GROUP; g++) {
-                    lv[g] = 0; yk[g] = 0; rv[g] = -1;
+                    yk[g] = 0;
+#pragma unroll
+                    for (int e = 0; e < L_ROWS; e++) { lv[g][e] = 0; rv[g][e] = -1; }
                     if (g < gcnt) {
                         const int lcnt = ups[g].krel_lcnt >> 16;
-                        if (s < lcnt) {
-                            lv[g] = LU[(size_t)(ups[g].lbeg + s) * T + t];
-                            rv[g] = P.rel[ups[g].roff + s];
-                        }
+#pragma unroll
+                        for (int e = 0; e < L_ROWS; e++)
+                            if (s + e * SL < lcnt) {
+                                lv[g][e] = LU[(size_t)(ups[g].lbeg + s + e * SL) * T + t];
+                                rv[g][e] = P.rel[ups[g].roff + s + e * SL];
+                            }
                         yk[g] = Yv[ups[g].k * T + t];
                     }
                 }
@@ -465,21 +480,26 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                         const int krel = up.krel_lcnt & 0xffff, lcnt = up.krel_lcnt >> 16;
                         const R m0 = xw[krel * T + t];
                         const R m1 = two ? xw1[krel * T + t] : (R)0;
-                        if (rv[g] >= 0) {
-                            const int tr = rv[g];
-                            const R l = lv[g];
+                        const R ykg = yk[g];
+                        // row tr of the panel's columns (and its right-hand side) minus the
+                        // multipliers times the source column's entry l
+                        auto apply = [&](int tr, R l) {
                             xw[tr * T + t] = fma(-m0, l, xw[tr * T + t]);
                             if (two) xw1[tr * T + t] = fma(-m1, l, xw1[tr * T + t]);
-                            if (tr == dr) ysl[t] = fma(-l, yk[g], ysl[t]);
-                            else if (two && tr == dr + 1) ysl1[t] = fma(-l, yk[g], ysl1[t]);
-                        }
-                        for (int r = s + SL; r < lcnt; r += SL) {
+                            if (tr == dr) ysl[t] = fma(-l, ykg, ysl[t]);
+                            else if (two && tr == dr + 1) ysl1[t] = fma(-l, ykg, ysl1[t]);
+                        };
+#pragma unroll
+                        for (int e = 0; e < L_ROWS; e++)
+                            if (rv[g][e] >= 0) apply(rv[g][e], lv[g][e]);
+                        for (int r = s + L_ROWS * SL; r < lcnt; r += 2 * SL) {
+                            const bool h2 = r + SL < lcnt;
                             const R l = LU[(size_t)(up.lbeg + r) * T + t];
                             const int tr = P.rel[up.roff + r];
-                            xw[tr * T + t] = fma(-m0, l, xw[tr * T + t]);
-                            if (two) xw1[tr * T + t] = fma(-m1, l, xw1[tr * T + t]);
-                            if (tr == dr) ysl[t] = fma(-l, yk[g], ysl[t]);
-                            else if (two && tr == dr + 1) ysl1[t] = fma(-l, yk[g], ysl1[t]);
+                            const R l2 = h2 ? LU[(size_t)(up.lbeg + r + SL) * T + t] : (R)0;
+                            const int tr2 = h2 ? P.rel[up.roff + r + SL] : 0;
+                            apply(tr, l);
+                            if (h2) apply(tr2, l2);
                         }
                         wave_sync();
                     }
