@@ -73,6 +73,14 @@ struct KArgs {
     int sched;                  // 0: level order, 1: elimination order
 };
 
+// Waits until every vector memory load this wavefront has issued has returned (vmcnt(0);
+// the encoding leaves the other counters unconstrained).  The memory counter also counts
+// stores, so a wait for a register loaded in an earlier loop iteration (whose distance
+// in operations the compiler cannot count) becomes a wait for everything, stores
+// included.  Placed where only loads are outstanding, this wait lets the compiler see
+// that nothing loaded is pending at the loop's back edge.
+__device__ __forceinline__ void wait_loads_returned() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -328,7 +336,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         const LuPanel *lud = P.lu_desc + (size_t)a.sched * P.n_panels;
         auto desc_chunk = [&](int c) -> int {
             const int qq = wave + NW * (8 * c + (lane >> 3));
-            return qq < P.n_panels ? reinterpret_cast<const int *>(lud)[(size_t)qq * 8 + (lane & 7)] : 0;
+            return reinterpret_cast<const int *>(lud)[(size_t)qq * 8 + (lane & 7)];   // padded table
         };
         auto desc_from = [&](int chunk, int k) -> LuPanel {
             LuPanel d;
@@ -337,11 +345,10 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             for (int f = 0; f < 8; f++) w[f] = __builtin_amdgcn_readlane(chunk, k * 8 + f);
             return d;
         };
-        auto upd_chunk_at = [&](int ua, int ue) -> int {      // records [ua, min(ua + 16, ue))
-            const int nu = min(16, ue - ua);
-            return lane < 4 * nu ? reinterpret_cast<const int *>(P.upd)[(size_t)ua * 4 + lane] : 0;
-        };
-        auto upd_chunk = [&](const LuPanel &d) -> int { return upd_chunk_at(d.u0, d.u1); };
+        // records [ua, ua + 16); only those below the panel's end are read back (the table
+        // is padded by one chunk)
+        auto upd_chunk_at = [&](int ua) -> int { return reinterpret_cast<const int *>(P.upd)[(size_t)ua * 4 + lane]; };
+        auto upd_chunk = [&](const LuPanel &d) -> int { return upd_chunk_at(d.u0); };
         R pa0[A_ROWS], pa1[A_ROWS], py0 = 0, py1 = 0;
         unsigned char pf[A_ROWS];
         int pupd = 0;
@@ -362,6 +369,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         int dch0 = desc_chunk(0), dch1 = desc_chunk(1);
         LuPanel pdc = desc_from(dch0, 0);         // the current panel's descriptor, kept in
         if (wave < P.n_panels) prefetch(pdc);     // scalar registers across iterations
+        wait_loads_returned();
         for (int q = wave, qi = 0; q < P.n_panels; q += NW, qi++) {
             const int kq = qi & 7;
             const LuPanel pd = pdc;
@@ -424,7 +432,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             // time.
             const int u0 = pd.u0, u1 = pd.u1;
             int ubase = u0, uc0 = ucur, uc1 = 0;
-            if (u1 - u0 > 16) uc1 = upd_chunk_at(u0 + 16, u1);
+            if (u1 - u0 > 16) uc1 = upd_chunk_at(u0 + 16);
             auto upd_rec = [&](int u) -> Update {
                 const int r = u - ubase;
                 Update x;
@@ -438,7 +446,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 if (ub - ubase >= 16) {
                     ubase += 16;
                     uc0 = uc1;
-                    if (u1 - ubase > 16) uc1 = upd_chunk_at(ubase + 16, u1);
+                    if (u1 - ubase > 16) uc1 = upd_chunk_at(ubase + 16);
                 }
                 Update ups[UPD_GROUP];
                 ups[0] = upd_rec(ub);
@@ -522,6 +530,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 for (int e = dr + 2 + s; e < cnt; e += SL) xw1[e * T + t] = xw1[e * T + t] / d1;
                 wave_sync();
             }
+            wait_loads_returned();
             for (int e = s; e < cnt; e += SL) {
                 LU[(size_t)(cs + e) * T + t] = xw[e * T + t];
                 if (two) LU[(size_t)(cs + cnt + e) * T + t] = xw1[e * T + t];
@@ -557,9 +566,10 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         const BsPanel *bsd = P.bs_desc + (size_t)a.sched * P.n_panels;
         auto bs_chunk = [&](int c) -> int {
             const int qq = wave + NW * (8 * c + (lane >> 3));
-            return qq < P.n_panels ? reinterpret_cast<const int *>(bsd)[(size_t)qq * 8 + (lane & 7)] : 0;
+            return reinterpret_cast<const int *>(bsd)[(size_t)qq * 8 + (lane & 7)];   // padded table
         };
         int bch0 = bs_chunk(0), bch1 = bs_chunk(1);
+        wait_loads_returned();
         for (int q = wave, qi = 0; q < P.n_panels; q += NW, qi++) {
             const int kq = qi & 7;
             BsPanel pd;
@@ -594,8 +604,9 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             for (int qb = q0; qb < q1; qb += SL) {
                 const int q = qb + s;
                 const bool in = q < q1;
-                const int c = in ? P.bs_col[q] : -1;
-                const int pq = in ? P.bs_pos[q] : 1;
+                const int c_all = P.bs_col[q], pq_all = P.bs_pos[q];   // padded tables
+                const int c = in ? c_all : -1;
+                const int pq = in ? pq_all : 1;
                 for (unsigned spins = 0;; ++spins) {
                     const bool ok = c < 0 || __hip_atomic_load(&done[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     if (__all(ok)) break;
@@ -626,6 +637,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 acc0 += __shfl_xor(acc0, off);
                 acc1 += __shfl_xor(acc1, off);
             }
+            wait_loads_returned();
             if (s == 0) {
                 R zl = 0;
                 if (two) {
@@ -947,13 +959,24 @@ static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *
 }
 
 // ------------------------------------------------------------------ plan upload
+// Zero padding after the tables the kernels read in whole chunks, so that those loads
+// need no bounds guard (a guarded load becomes a masked load plus a register copy, and the
+// copy makes the compiler wait for the load at once): update records are read 16 at a
+// time from a panel's first record, back-substitution entries SL at a time (SL <= 16)
+// from a row's first entry, and panel descriptors 8 per wavefront, two chunks ahead, so
+// up to 23 * NW (NW <= 16) beyond the last panel.
+constexpr size_t PAD_UPD = 16 * sizeof(Update);
+constexpr size_t PAD_BS = 64 * sizeof(int32_t);
+constexpr size_t PAD_DESC = 24 * 16 * sizeof(LuPanel);
+static_assert(sizeof(LuPanel) == sizeof(BsPanel), "descriptor tables share one padding");
+
 struct DevOffsets {
     size_t bytes = 0;
     template <typename V>
-    size_t add(const V &v)
+    size_t add(const V &v, size_t pad = 0)
     {
         size_t o = bytes;
-        bytes = align256(bytes + v.size() * sizeof(typename V::value_type) + 1);
+        bytes = align256(bytes + v.size() * sizeof(typename V::value_type) + pad + 1);
         return o;
     }
 };
@@ -965,11 +988,11 @@ static int upload(Plan *pl)
     DevOffsets off;
     const size_t o_yrp = off.add(h.yrp), o_yci = off.add(h.yci);
     const size_t o_jpos = off.add(h.jpos), o_isj = off.add(h.isj), o_rel = off.add(h.rel);
-    const size_t o_upd = off.add(h.upd);
-    const size_t o_bpos = off.add(h.bs_pos), o_bcol = off.add(h.bs_col);
+    const size_t o_upd = off.add(h.upd, PAD_UPD);
+    const size_t o_bpos = off.add(h.bs_pos, PAD_BS), o_bcol = off.add(h.bs_col, PAD_BS);
     const size_t o_pe = off.add(h.bus_peq), o_qe = off.add(h.bus_qeq);
     const size_t o_perm = off.add(h.perm);
-    const size_t o_lud = off.add(h.lu_desc), o_bsd = off.add(h.bs_desc);
+    const size_t o_lud = off.add(h.lu_desc, PAD_DESC), o_bsd = off.add(h.bs_desc, PAD_DESC);
     std::vector<char> host(off.bytes, 0);
     auto put = [&](size_t o, const auto &v) {
         if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * sizeof(v[0]));
