@@ -74,7 +74,11 @@ typedef struct {
                               the angle/|V| column pairs of PQ buses): 0 = by level of the
                               column DAG (default), 1 = elimination order; both are
                               topological, results differ only by rounding order          */
-    int32_t reserved[4];
+    int32_t long_slots;    /* shared LDS working columns for the panels longer than
+                              info.slot_rows (1..8): more let more of the serial tail of the
+                              elimination overlap, at the cost of LDS; 0 = automatic (the
+                              most that keep the resident workgroups the batch can use)    */
+    int32_t reserved[3];
 } pf_solve_opts;
 
 /*
@@ -112,12 +116,16 @@ int pf_plan_lu_pattern(pf_plan plan, int32_t *col_ptr, int32_t *row_idx, int32_t
  * The refactorization schedule of one panel order (order 0: by level, 1: elimination
  * order) [host, n_panels = info.n_panels entries each]: first[q] is the first column of
  * the q-th panel in that order and width[q] its column count (1, or 2 for the angle/|V|
- * pair of a PQ bus); slot[q] is -1 for a panel that uses its wavefront's short working
- * columns, else the shared long slot it takes, and wait[q] the column whose publication
- * frees that slot (-1: none).  The kernel relies on: every update source of a panel lies
- * in an earlier panel of the order, and every slot wait names an earlier long panel.
+ * pair of a PQ bus); long_rank[q] is -1 for a panel that uses its wavefront's short
+ * working columns (at most info.slot_rows rows), else its rank among the order's long
+ * panels, and prev_long[q] the first column of the long panel one rank earlier (-1: none).
+ * A launch with L long slots (pf_solve_opts.long_slots) gives the long panel of rank r
+ * slot r mod L once the one of rank r - L has published.  The kernel relies on: every
+ * update source of a panel lies in an earlier panel of the order, and ranks increase
+ * along the order (so every slot wait names an earlier panel).
  */
-int pf_plan_schedule(pf_plan plan, int32_t order, int32_t *first, int32_t *width, int32_t *slot, int32_t *wait);
+int pf_plan_schedule(pf_plan plan, int32_t order, int32_t *first, int32_t *width, int32_t *long_rank,
+                     int32_t *prev_long);
 
 /* Workspace bytes pf_solve_batch needs for `batch` instances with `opts` (NULL = default). */
 size_t pf_workspace_bytes(pf_plan plan, int32_t batch, const pf_solve_opts *opts);

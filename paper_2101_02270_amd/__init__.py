@@ -48,7 +48,7 @@ class _PlanInfo(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tile", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("schedule", ctypes.c_int32), ("long_slots", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class _QueueInfo(ctypes.Structure):
@@ -183,19 +183,22 @@ class Plan:
         return cp, ri, lv
 
     def schedule(self, order: int = 0):
-        """(first column, width, long slot, slot wait) of every panel in processing order."""
+        """(first column, width, rank among the long panels or -1, first column of the long
+        panel one rank earlier or -1) of every panel in processing order."""
         np_ = self.info["n_panels"]
         out = [np.zeros(np_, np.int32) for _ in range(4)]
         _check(lib().pf_plan_schedule(self._h, int(order), *[a.ctypes.data_as(_i32p) for a in out]),
                "pf_plan_schedule")
         return tuple(out)
 
-    def resolve(self, batch: int, precision=PF_FP64, tile=0, waves=0, schedule=0) -> dict:
+    def resolve(self, batch: int, precision=PF_FP64, tile=0, waves=0, schedule=0, long_slots=0) -> dict:
         """The configuration a solve of batch instances would use (pf_resolve_opts)."""
         o = _Opts()
-        _check(lib().pf_resolve_opts(self._h, int(batch), ctypes.byref(_Opts(precision, tile, waves, schedule)),
+        _check(lib().pf_resolve_opts(self._h, int(batch),
+                                     ctypes.byref(_Opts(precision, tile, waves, schedule, long_slots)),
                                      ctypes.byref(o)), "pf_resolve_opts")
-        return {"precision": o.precision, "tile": o.tile, "waves": o.waves, "schedule": o.schedule}
+        return {"precision": o.precision, "tile": o.tile, "waves": o.waves, "schedule": o.schedule,
+                "long_slots": o.long_slots}
 
     def workspace_bytes(self, batch: int, precision=PF_FP64, tile=0, waves=0) -> int:
         o = _Opts(precision, tile, waves)
@@ -268,7 +271,7 @@ def _as_pairs(x, name):
 def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
                 precision: int = PF_FP64, tile: int = 0, waves: int = 0, workspace=None,
                 stream=None, out: Optional[Result] = None, schedule: int = 0,
-                v_fallback=None) -> Result:
+                v_fallback=None, long_slots: int = 0) -> Result:
     """Run pf_solve_batch on device tensors: ybus complex128 [nnz_y] (or [B][nnz_y]: one set of
     values per instance), sbus complex128 [B][n],
     v0 float64 [B][n][2].  With v_fallback (same shape as v0) pf_solve_batch_warm runs
@@ -285,7 +288,7 @@ def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 1
                      iters=torch.empty(B, dtype=torch.int32, device=v0.device),
                      converged=torch.empty(B, dtype=torch.uint8, device=v0.device),
                      status=torch.empty(B, dtype=torch.int8, device=v0.device))
-    opts = _Opts(precision, tile, waves, schedule)
+    opts = _Opts(precision, tile, waves, schedule, long_slots)
     workspace, wp, avail = _workspace(plan, B, opts, workspace)
     outs = (_vp(out.v.data_ptr()), _vp(out.iters.data_ptr()), _vp(out.converged.data_ptr()),
             _vp(out.status.data_ptr()), _stream_ptr(stream))
@@ -348,7 +351,7 @@ def tune(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
          precision: int = PF_FP64, waves: int = 0, reps: int = 2, force: bool = False,
          stream=None):
     """pf_tune on device tensors shaped as for solve_batch.  Returns
-    ({"precision", "tile", "waves", "schedule"}, mean ms per solve)."""
+    ({"precision", "tile", "waves", "schedule", "long_slots"}, mean ms per solve)."""
     torch = _torch()
     B = int(v0.shape[0])
     yp, _, _ = _ybus_view(plan, ybus)
@@ -361,7 +364,7 @@ def tune(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
                        _stream_ptr(stream))
     _check(rc, "pf_tune")
     return ({"precision": best.precision, "tile": best.tile, "waves": best.waves,
-             "schedule": best.schedule}, ms.value)
+             "schedule": best.schedule, "long_slots": best.long_slots}, ms.value)
 
 
 class Queue:
@@ -378,7 +381,7 @@ class Queue:
 
     def add(self, plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
             precision: int = PF_FP64, tile: int = 0, waves: int = 0, schedule: int = 0,
-            ticks: bool = True) -> Result:
+            ticks: bool = True, long_slots: int = 0) -> Result:
         torch = _torch()
         B = int(v0.shape[0])
         yp, yv, _ = _ybus_view(plan, ybus)
@@ -391,7 +394,7 @@ class Queue:
                      converged=torch.empty(B, dtype=torch.uint8, device=dev),
                      status=torch.empty(B, dtype=torch.int8, device=dev))
         out.ticks = torch.zeros(B, dtype=torch.int64, device=dev) if ticks else None
-        opts = _Opts(precision, tile, waves, schedule)
+        opts = _Opts(precision, tile, waves, schedule, long_slots)
         rc = lib().pf_queue_add(self._h, plan._h, B, yp, sp, vp, float(tol), int(max_iter),
                                 ctypes.byref(opts), _vp(out.v.data_ptr()), _vp(out.iters.data_ptr()),
                                 _vp(out.converged.data_ptr()), _vp(out.status.data_ptr()),

@@ -32,10 +32,10 @@ struct Update {
 
 // Everything one refactorization panel needs, in processing order (one load per panel):
 // first column with the pair flag in bit 30, first entry and entry count of the column,
-// position of the diagonal inside it, the column's update range, and its working-column
-// slot and slot wait (see HostPlan::lslot).
+// position of the diagonal inside it, the column's update range, and its rank among the
+// order's long panels (-1: short; see HostPlan::long_rank).
 struct LuPanel {
-    int32_t j2, cs, cnt, dr, u0, u1, slot, wait;
+    int32_t j2, cs, cnt, dr, u0, u1, lrank, pad;
 };
 
 // The same for back substitution: first row with the pair flag in bit 30, first entries of
@@ -45,11 +45,6 @@ struct BsPanel {
     int32_t j2, cs, cs1, dr, q0, q1, pu, pad;
 };
 
-// Working-column slot of a panel: slot index (-1: the wavefront's short slot) and the
-// column whose publication frees the slot (-1: none).
-struct SlotRef {
-    int32_t slot, wait;
-};
 
 // Everything pf_analyze derives from the pattern, on the host.
 struct HostPlan {
@@ -85,13 +80,15 @@ struct HostPlan {
     // the column DAG) and by back-substitution level (topological for the row DAG)
     std::vector<int32_t> lu_seq, bs_seq;
     // working-column slots of the refactorization: a panel of at most slot_rows rows uses
-    // its wavefront's own slot; a longer panel uses one of n_long shared slots.  For each
-    // of the two panel orders (level, elimination) and each panel: {slot, column to wait
-    // for}: the r-th long panel of an order takes slot r mod n_long once the (r - n_long)-th
-    // has published, so slots are handed out in topological order; {-1, -1} for short
-    // panels.
-    int slot_rows = 0, n_long = 0;
-    std::vector<int32_t> lslot;                   // [2][n_panels][2]
+    // its wavefront's own slot; a longer panel uses one of the launch's L shared slots (L
+    // is chosen per launch from the LDS left over).  For each of the two panel orders
+    // (level, elimination): the rank of each panel among the order's long panels (-1 for
+    // a short panel) and the first column of the long panel of each rank.  The long panel
+    // of rank r takes slot r mod L once the one of rank r - L has published, so slots are
+    // handed out in topological order.
+    int slot_rows = 0, n_longp = 0;
+    std::vector<int32_t> long_rank;               // [2][n_panels]
+    std::vector<int32_t> long_first;              // [2][n_longp]
     // per order (0: level, 1: elimination) and position in that order
     std::vector<LuPanel> lu_desc;                 // [2][n_panels]
     std::vector<BsPanel> bs_desc;                 // [2][n_panels]
@@ -114,7 +111,7 @@ struct DevPlan {
     const int32_t *bus_peq, *bus_qeq;
     const LuPanel *lu_desc;
     const BsPanel *bs_desc;
-    int n_panels, slot_rows, n_long;
+    int n_panels, slot_rows;
 };
 
 struct Plan {

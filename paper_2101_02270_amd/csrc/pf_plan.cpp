@@ -354,26 +354,26 @@ int analyze(int n, int nnzy, const int32_t *row_ptr, const int32_t *col_idx,
         });
 
         // short working columns cover all but the longest ~4% of panels (at least 16 rows,
-        // a multiple of 8); the rest share two long slots
+        // a multiple of 8); the rest share the launch's long slots
         std::vector<int> rows(np);
         for (int q = 0; q < np; q++) rows[q] = h.col_ptr[h.panel_ptr[q] + 1] - h.col_ptr[h.panel_ptr[q]];
         std::vector<int> sorted_rows(rows);
         std::sort(sorted_rows.begin(), sorted_rows.end());
         const int p96 = np ? sorted_rows[std::min(np - 1, (int)(0.96 * np))] : 0;
         h.slot_rows = std::max(16, (p96 + 7) / 8 * 8);
-        if (h.slot_rows >= h.max_col) { h.slot_rows = h.max_col; h.n_long = 0; }
-        else h.n_long = 2;
-        h.lslot.assign((size_t)4 * np, -1);
+        if (h.slot_rows >= h.max_col) h.slot_rows = h.max_col;
+        h.n_longp = 0;
+        for (int q = 0; q < np; q++) h.n_longp += rows[q] > h.slot_rows;
+        h.long_rank.assign((size_t)2 * np, -1);
+        h.long_first.assign((size_t)2 * h.n_longp, -1);
         for (int order = 0; order < 2; order++) {
-            std::vector<int> long_cols;            // first column of each long panel in this order
+            int r = 0;
             for (int q = 0; q < np; q++) {
                 const int pi = order == 0 ? h.lu_seq[q] : q;
                 if (rows[pi] <= h.slot_rows) continue;
-                const int r = (int)long_cols.size();
-                int32_t *e = &h.lslot[((size_t)order * np + pi) * 2];
-                e[0] = r % h.n_long;
-                e[1] = r >= h.n_long ? long_cols[r - h.n_long] : -1;
-                long_cols.push_back(h.panel_ptr[pi]);
+                h.long_rank[(size_t)order * np + pi] = r;
+                h.long_first[(size_t)order * h.n_longp + r] = h.panel_ptr[pi];
+                r++;
             }
         }
     }
@@ -389,10 +389,9 @@ int analyze(int n, int nnzy, const int32_t *row_ptr, const int32_t *col_idx,
                     const int pi = order == 0 ? h.lu_seq[q] : q;
                     const int j = h.panel_ptr[pi];
                     const int two = h.panel_ptr[pi + 1] - j == 2;
-                    const int32_t *ls = &h.lslot[((size_t)order * np + pi) * 2];
                     h.lu_desc[(size_t)order * np + q] =
                         LuPanel{j | (two << 30), h.col_ptr[j], h.col_ptr[j + 1] - h.col_ptr[j], h.col_diag[j],
-                                h.upd_ptr[j], h.upd_ptr[j + 1], ls[0], ls[1]};
+                                h.upd_ptr[j], h.upd_ptr[j + 1], h.long_rank[(size_t)order * np + pi], 0};
                 }
                 {
                     const int pi = order == 0 ? h.bs_seq[q] : np - 1 - q;

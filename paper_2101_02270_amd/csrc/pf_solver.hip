@@ -49,6 +49,7 @@ enum Mode { MODE_SOLVE = 0, MODE_MISMATCH = 1, MODE_FACTOR = 2, MODE_STEP = 3 };
 
 constexpr int UPD_GROUP = 3;     // column updates whose operand loads are issued together
 constexpr int L_ROWS = 2;        // rows of each source column per lane loaded with its group
+constexpr int kMaxLong = 8;      // most shared long working-column slots of a launch
 
 struct KArgs {
     DevPlan p;
@@ -60,6 +61,8 @@ struct KArgs {
     const double *v_fb;         // [B][n][2] restart point after a failed first attempt (may be null)
     double tol;
     int max_iter, batch, mode;
+    int n_long;                 // shared long working-column slots of the refactorization
+    unsigned n_long_inv;        // ceil(2^32 / n_long) for n_long >= 2
     char *ws;
     size_t tile_bytes, off_y, off_vec;   // byte offsets inside one tile's block
     double *v_out;
@@ -113,6 +116,24 @@ __device__ __forceinline__ void wait_published(unsigned char *flags, int j, int 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// The same bounded wait for an LDS counter to reach a value (counters only grow).
+__device__ __forceinline__ void wait_count(int *ctr, int target, int *err)
+{
+    for (unsigned spins = 0;; ++spins) {
+        const int v = __builtin_amdgcn_readfirstlane(__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (v >= target) break;
+        const int e = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (e) break;
+        if (spins >= (1u << 22)) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // The whole Newton loop of one tile (T instances) by one workgroup.  Called by the
 // one-tile-per-workgroup kernel and by the persistent multi-pattern queue kernel.
 template <typename R, int T, int NW>
@@ -131,6 +152,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     __shared__ double s_prevf[T];
     __shared__ double s_normf[T];
     __shared__ int s_any, s_err;
+    __shared__ int s_lgen[kMaxLong];    // publications seen by each long working-column slot
 
     const DevPlan &P = a.p;
     const int tid = threadIdx.x;
@@ -159,10 +181,10 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     // publication byte per column
     R *const short_base = reinterpret_cast<R *>(smem_raw);
     R *const long_base = short_base + (size_t)NW * 2 * P.slot_rows * T;
-    R *ysl = long_base + (size_t)P.n_long * 2 * P.max_col * T + (size_t)wave * 2 * T;
+    R *ysl = long_base + (size_t)a.n_long * 2 * P.max_col * T + (size_t)wave * 2 * T;
     R *ysl1 = ysl + T;
     unsigned char *done = reinterpret_cast<unsigned char *>(
-        long_base + (size_t)P.n_long * 2 * P.max_col * T + (size_t)NW * 2 * T);
+        long_base + (size_t)a.n_long * 2 * P.max_col * T + (size_t)NW * 2 * T);
     int *err = &s_err;
 
     // ---- boundary layout [B][n][2] -> tile layout [n][T]
@@ -311,10 +333,19 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             if (a.mode != MODE_SOLVE) return;
             break;
         }
+        // every instance ends within max_iter + 3 passes (updates over both attempts, the
+        // restart pass and the final test); a tile still running well past that has lost
+        // its state and reports an internal error instead of looping on
+        if (it > 2 * a.max_iter + 4) {
+            if (tid == 0) s_err = 1;
+            __syncthreads();
+            break;
+        }
 
         // ============================ LU: Jacobian -> refactorization -> forward substitution
         for (int w = tid; w < N; w += NT)
             __hip_atomic_store(&done[w], (unsigned char)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (tid < kMaxLong) __hip_atomic_store(&s_lgen[tid], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __syncthreads();
         // Panels (one column, or the angle/|V| pair of a PQ bus sharing one row list) in
         // level order, round-robin over the wavefronts.  The order is topological, so the
@@ -384,18 +415,22 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 dch1 = desc_chunk((qi >> 3) + 2);
             }
             R *xw, *xw1;
-            {
-                const SlotRef ls{pd.slot, pd.wait};
-                if (ls.slot < 0) {
-                    xw = short_base + (size_t)wave * 2 * P.slot_rows * T;
-                    xw1 = xw + (size_t)P.slot_rows * T;
-                } else {
-                    // a long panel: its shared slot is free once the panel that used it
-                    // before (earlier in the same topological order) has published
-                    if (ls.wait >= 0) wait_published(done, ls.wait, err);
-                    xw = long_base + (size_t)ls.slot * 2 * P.max_col * T;
-                    xw1 = xw + (size_t)P.max_col * T;
-                }
+            // a long panel of rank r takes slot r mod n_long once the slot has seen r / n_long
+            // publications, i.e. once the long panel of rank r - n_long (earlier in the same
+            // topological order) has published
+            // (the quotient by a multiply-high with the rounded-up reciprocal, exact for ranks
+            // below 2^29; an integer division would be emulated on vector registers; with one
+            // slot the reciprocal 2^32 does not fit and the rank is the quotient)
+            const int lgen = pd.lrank < 0 ? 0
+                             : a.n_long == 1 ? pd.lrank : (int)__umulhi((unsigned)pd.lrank, a.n_long_inv);
+            const int lslot = pd.lrank < 0 ? -1 : pd.lrank - lgen * a.n_long;
+            if (lslot < 0) {
+                xw = short_base + (size_t)wave * 2 * P.slot_rows * T;
+                xw1 = xw + (size_t)P.slot_rows * T;
+            } else {
+                if (lgen > 0) wait_count(&s_lgen[lslot], lgen, err);
+                xw = long_base + (size_t)lslot * 2 * P.max_col * T;
+                xw1 = xw + (size_t)P.max_col * T;
             }
             // the panel's Jacobian values (written by the mismatch pass; fill positions read
             // as zero; both columns of a pair share the row list and the fill pattern) and
@@ -543,6 +578,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __hip_atomic_store(&done[j], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (two) __hip_atomic_store(&done[j + 1], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (lslot >= 0) __hip_atomic_store(&s_lgen[lslot], lgen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         __syncthreads();
         if (tid < T && s_piv[t] && s_active[t] && !s_reset[t] && a.mode == MODE_SOLVE) {
@@ -733,7 +769,7 @@ __global__ void queue_reset_kernel(int *counters, int n, unsigned long long *t0)
 
 // ------------------------------------------------------------------ launch configuration
 struct Config {
-    int precision, tile, waves, schedule;
+    int precision, tile, waves, schedule, n_long;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -755,7 +791,7 @@ static TileLayout tile_layout(const HostPlan &h, const Config &c)
 static size_t lds_bytes(const HostPlan &h, const Config &c)
 {
     const size_t rs = c.precision == PF_FP32_LU ? 4 : 8;
-    return ((size_t)c.waves * 2 * ((size_t)h.slot_rows * c.tile + c.tile) + (size_t)h.n_long * 2 * h.max_col * c.tile) * rs +
+    return ((size_t)c.waves * 2 * ((size_t)h.slot_rows * c.tile + c.tile) + (size_t)c.n_long * 2 * h.max_col * c.tile) * rs +
            (size_t)h.N;
 }
 
@@ -769,12 +805,21 @@ static constexpr size_t kLdsLimit = 160 * 1024 - 8192;
 // limited by LDS and by the 16 wavefronts per CU that four waves per SIMD allow.  Within
 // 10% of the lowest cost, 8-wave workgroups are preferred (measured best when the model
 // ties), then more resident workgroups.  batch <= 0 assumes a batch much larger than the GPU.
+// The candidates are costed with two long slots.  An automatic long-slot count then takes
+// the most slots (up to 8) that keep the resident workgroups per CU the batch can use:
+// the long panels form the serial tail of the elimination, and a long panel can only
+// start once the panel that held its slot before has published, so more slots let more
+// of the tail overlap (measured 12-30% faster on 1350- and 9000-bus grids).
 static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c, std::string &err,
                            int64_t batch = 0)
 {
     c.precision = o ? o->precision : PF_FP64;
     c.schedule = o ? o->schedule : 0;
     if (c.schedule != 0 && c.schedule != 1) { err = "schedule must be 0 or 1"; return false; }
+    const int long_slots = o ? o->long_slots : 0;
+    if (long_slots < 0 || long_slots > kMaxLong) { err = "long_slots must be 0..8"; return false; }
+    const int nl_max = std::min(kMaxLong, h.n_longp);
+    c.n_long = long_slots ? std::min(long_slots, nl_max) : std::min(2, nl_max);
     const int tile = o ? o->tile : 0, waves = o ? o->waves : 0;
     if (c.precision != PF_FP64 && c.precision != PF_FP32_LU) { err = "unknown precision"; return false; }
     const bool fp64 = c.precision == PF_FP64;
@@ -814,6 +859,18 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
         }
         c.tile = pick->tile;
         c.waves = pick->waves;
+        if (!long_slots && c.n_long > 0) {
+            auto resident = [&](int nl) {
+                Config k = c;
+                k.n_long = nl;
+                const size_t lds = lds_bytes(h, k);
+                return lds > kLdsLimit ? 0 : (int)std::min<size_t>(kLdsLimit / lds, 16 / c.waves);
+            };
+            const int usable = (int)std::max(1.0, std::ceil(std::ceil(b / c.tile) / 256.0));
+            const int keep = std::min(resident(c.n_long), usable);
+            for (int nl = c.n_long + 1; nl <= nl_max; nl++)
+                if (resident(nl) >= keep) c.n_long = nl;
+        }
         return true;
     }
     err = "the longest LU column (" + std::to_string(h.max_col) + " entries) does not fit in LDS for any "
@@ -927,6 +984,14 @@ static int make_args(Plan *pl, const Config &c, int32_t batch, const double *ybu
     a.ws = reinterpret_cast<char *>(workspace);
     a.tile_bytes = L.bytes; a.off_y = L.off_y; a.off_vec = L.off_vec;
     a.sched = c.schedule;
+    // the kernel derives a long panel's slot from its rank with this reciprocal; a count
+    // outside 1..kMaxLong (0 only without long panels) would index past the slot counters
+    if (c.n_long < (h.n_longp > 0 ? 1 : 0) || c.n_long > kMaxLong) {
+        set_error("internal: long-slot count out of range");
+        return PF_EINVAL;
+    }
+    a.n_long = c.n_long;
+    a.n_long_inv = c.n_long >= 2 ? (unsigned)((0x100000000ull + c.n_long - 1) / c.n_long) : 0u;
     a.v_out = v_out; a.iters_out = iters_out; a.conv_out = conv_out; a.status_out = status_out;
     a.aux_out = aux; a.aux2_out = aux2;
     return PF_OK;
@@ -1022,7 +1087,6 @@ static int upload(Plan *pl)
     d.bs_desc = (const BsPanel *)(D + o_bsd);
     d.n_panels = (int)h.panel_ptr.size() - 1;
     d.slot_rows = h.slot_rows;
-    d.n_long = h.n_long;
     return PF_OK;
 }
 
@@ -1354,10 +1418,11 @@ int pf_plan_lu_pattern(pf_plan plan, int32_t *col_ptr, int32_t *row_idx, int32_t
     return PF_OK;
 }
 
-int pf_plan_schedule(pf_plan plan, int32_t order, int32_t *first, int32_t *width, int32_t *slot, int32_t *wait)
+int pf_plan_schedule(pf_plan plan, int32_t order, int32_t *first, int32_t *width, int32_t *long_rank,
+                     int32_t *prev_long)
 {
     Plan *pl = reinterpret_cast<Plan *>(plan);
-    if (!pl || !first || !width || !slot || !wait) { set_error("null argument"); return PF_EINVAL; }
+    if (!pl || !first || !width || !long_rank || !prev_long) { set_error("null argument"); return PF_EINVAL; }
     if (order != 0 && order != 1) { set_error("order must be 0 or 1"); return PF_EINVAL; }
     const HostPlan &h = pl->h;
     const int np = (int)h.panel_ptr.size() - 1;
@@ -1365,8 +1430,8 @@ int pf_plan_schedule(pf_plan plan, int32_t order, int32_t *first, int32_t *width
         const LuPanel &d = h.lu_desc[(size_t)order * np + q];
         first[q] = d.j2 & ((1 << 30) - 1);
         width[q] = 1 + ((d.j2 >> 30) & 1);
-        slot[q] = d.slot;
-        wait[q] = d.wait;
+        long_rank[q] = d.lrank;
+        prev_long[q] = d.lrank > 0 ? h.long_first[(size_t)order * h.n_longp + d.lrank - 1] : -1;
     }
     return PF_OK;
 }
@@ -1394,6 +1459,7 @@ int pf_resolve_opts(pf_plan plan, int32_t batch, const pf_solve_opts *opts, pf_s
     out->tile = c.tile;
     out->waves = c.waves;
     out->schedule = c.schedule;
+    out->long_slots = c.n_long;
     return PF_OK;
 }
 
@@ -1578,14 +1644,24 @@ int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
         for (int w : wv) {
             if (waves && w != waves) continue;
             for (int sc = 0; sc < 2; sc++) {
-                pf_solve_opts o{};
-                o.precision = precision;
-                o.tile = precision == PF_FP64 ? tiles64[ti] : tiles32[ti];
-                o.waves = w;
-                o.schedule = sc;
-                Config c;
-                std::string err;
-                if (resolve_config(pl->h, &o, c, err) && lds_bytes(pl->h, c) <= kLdsLimit) cand.push_back(o);
+                // long-slot counts: the automatic choice for this batch, and 2, 4, 8 (each
+                // resolved count once)
+                std::vector<int> seen;
+                for (const int ls : {0, 2, 4, 8}) {
+                    pf_solve_opts o{};
+                    o.precision = precision;
+                    o.tile = precision == PF_FP64 ? tiles64[ti] : tiles32[ti];
+                    o.waves = w;
+                    o.schedule = sc;
+                    o.long_slots = ls;
+                    Config c;
+                    std::string err;
+                    if (!resolve_config(pl->h, &o, c, err, batch) || lds_bytes(pl->h, c) > kLdsLimit) continue;
+                    if (std::find(seen.begin(), seen.end(), c.n_long) != seen.end()) continue;
+                    seen.push_back(c.n_long);
+                    o.long_slots = c.n_long;
+                    cand.push_back(o);
+                }
             }
         }
     if (cand.empty()) { set_error("no configuration fits in LDS"); return PF_EINVAL; }

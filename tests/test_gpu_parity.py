@@ -293,6 +293,28 @@ def test_batch_of_one_and_deterministic(systems):
     compare_solve(osys, osys.solve(sc.sbus, sc.v0), r1)
 
 
+@pytest.mark.parametrize("name,B,prec,tile,waves", [("c1_1350bus", 48, pf.PF_FP64, 8, 8),
+                                                     ("c1_1350bus", 48, pf.PF_FP32_LU, 16, 8),
+                                                     ("c2_9000bus", 16, pf.PF_FP64, 4, 8)])
+def test_long_slot_count_does_not_change_results(systems, name, B, prec, tile, waves):
+    """The number of shared long working columns only decides where a long panel's working
+    column lives in LDS and how much of the elimination's tail overlaps; the arithmetic and
+    its order are unchanged, so every count gives bit-identical results.  One count is also
+    checked against the oracle."""
+    g, yb, osys, plan = systems[name]
+    sc = gg.make_scenarios(g, B, 31, "mc")
+    y, s, v = to_dev(yb, sc)
+    kw = dict(precision=prec, tile=tile, waves=waves)
+    ref = pf.solve_batch(plan, y, s, v, long_slots=1, **kw)
+    for ls in (2, 3, 5, 8, 0):
+        print(f"{name} precision {prec} long_slots {ls}", flush=True)
+        r = pf.solve_batch(plan, y, s, v, long_slots=ls, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(r.v, ref.v) and torch.equal(r.iters, ref.iters) and torch.equal(r.status, ref.status), ls
+    if prec == pf.PF_FP64 and name == "c1_1350bus":
+        compare_solve(osys, osys.solve(sc.sbus, sc.v0), ref)
+
+
 def test_natural_and_user_orderings_agree(systems):
     g, yb, osys, _ = systems["c4_100bus"]
     sc = gg.make_scenarios(g, 33, 9, "mc")

@@ -191,13 +191,13 @@ def test_queue_without_device_reports_error():
 def test_schedule_is_topological_and_slots_are_handed_out_in_order(name, order):
     """The refactorization's deadlock-freedom rests on two properties of each panel order:
     every column-to-column update source (U(k, j) != 0, k < j) lies in an earlier panel,
-    and every long panel's slot wait names the first column of an earlier long panel that
-    used the same slot.  Checked from the LU pattern, independently of the plan's own
-    construction."""
+    and the long panels' ranks increase along the order, so that with any number L of
+    long slots the panel of rank r - L, whose publication frees the slot of rank r, comes
+    earlier.  Checked from the LU pattern, independently of the plan's own construction."""
     g = gg.grid(name)
     plan = pf.Plan.from_ybus(gg.ybus(g), g.bus_type)
     cp, ri, _ = plan.lu_pattern()
-    first, width, slot, wait = plan.schedule(order)
+    first, width, rank, prev = plan.schedule(order)
     N = plan.N
     assert np.array_equal(np.sort(np.concatenate([np.arange(f, f + w) for f, w in zip(first, width)])), np.arange(N))
     pos = np.empty(N, np.int64)
@@ -209,18 +209,15 @@ def test_schedule_is_topological_and_slots_are_handed_out_in_order(name, order):
         srcs = srcs[pos[srcs] != pos[j]]            # the pair's first column is internal
         assert (pos[srcs] < pos[j]).all(), j
     info = plan.info
-    long_q = np.flatnonzero(slot >= 0)
+    long_q = np.flatnonzero(rank >= 0)
     rows_of = (cp[first + 1] - cp[first])
     assert (rows_of[long_q] > info["slot_rows"]).all()
-    assert (rows_of[slot < 0] <= info["slot_rows"]).all()
-    last_user = {}
-    for q in long_q:
-        s = int(slot[q])
-        if s in last_user:
-            assert wait[q] == first[last_user[s]] and last_user[s] < q
-        else:
-            assert wait[q] == -1
-        last_user[s] = q
+    assert (rows_of[rank < 0] <= info["slot_rows"]).all()
+    assert np.array_equal(rank[long_q], np.arange(len(long_q)))       # ranks in order
+    assert (prev[rank < 0] == -1).all()
+    if len(long_q):
+        assert prev[long_q[0]] == -1
+        assert np.array_equal(prev[long_q[1:]], first[long_q[:-1]])   # previous long panel
 
 
 def test_automatic_launch_configuration():
@@ -238,6 +235,17 @@ def test_automatic_launch_configuration():
     p2 = pf.Plan.from_ybus(gg.ybus(g2), g2.bus_type)
     r = p2.resolve(2000)
     assert (r["tile"], r["waves"]) == (8, 16)
-    for bad in (dict(tile=32), dict(waves=3), dict(schedule=2), dict(precision=7)):
+    # long slots: as many as keep the resident workgroups the batch can use (measured:
+    # 1350-bus x 10000 best with 4 at two workgroups per CU; 9000-bus x 2000, one
+    # generation of tiles, takes as many as fit)
+    assert p1.resolve(10000)["long_slots"] == 4
+    assert p1.resolve(10000, precision=pf.PF_FP32_LU)["long_slots"] == 4
+    assert p2.resolve(2000)["long_slots"] == 3
+    assert p2.resolve(2000, precision=pf.PF_FP32_LU)["long_slots"] == 8
+    assert p1.resolve(10000, long_slots=2)["long_slots"] == 2
+    g0 = gg.grid("c0_14bus")
+    assert pf.Plan.from_ybus(gg.ybus(g0), g0.bus_type).resolve(64)["long_slots"] == 0    # no long panel
+    for bad in (dict(tile=32), dict(waves=3), dict(schedule=2), dict(precision=7), dict(long_slots=9),
+                dict(long_slots=-1)):
         with pytest.raises(pf.PfError):
             p1.resolve(100, **bad)
