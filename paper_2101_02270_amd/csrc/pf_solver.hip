@@ -800,16 +800,16 @@ static constexpr size_t kLdsLimit = 160 * 1024 - 8192;
 
 // Explicit tile/waves are validated.  A zero picks the value that minimises a latency
 // model of the solve: a tile's time grows with the panels each wavefront handles in turn
-// (n_panels / waves) and mildly with the rows per lane (1 + T/32); tiles run in
+// (n_panels / waves), mildly with the rows per lane (1 + T/32), and falls with the long
+// working-column slots L as 0.76 + 0.48 / L (fitted to the 1350-bus grid: 32.2 / 29.1 /
+// 27.6 ms with 2 / 3 / 4 slots): the long panels form the serial tail of the elimination,
+// and a long panel can only start once the panel that held its slot before has
+// published, so more slots let more of the tail overlap.  Tiles run in
 // max(1, tiles / resident workgroups) generations, where the resident workgroups per CU are
-// limited by LDS and by the 16 wavefronts per CU that four waves per SIMD allow.  Within
-// 10% of the lowest cost, 8-wave workgroups are preferred (measured best when the model
-// ties), then more resident workgroups.  batch <= 0 assumes a batch much larger than the GPU.
-// The candidates are costed with two long slots.  An automatic long-slot count then takes
-// the most slots (up to 8) that keep the resident workgroups per CU the batch can use:
-// the long panels form the serial tail of the elimination, and a long panel can only
-// start once the panel that held its slot before has published, so more slots let more
-// of the tail overlap (measured 12-30% faster on 1350- and 9000-bus grids).
+// limited by LDS and by the 16 wavefronts per CU that four waves per SIMD allow.  Within 3%
+// of the lowest cost, 8-wave workgroups are preferred, then more resident workgroups.  An
+// automatic L is, for each candidate, the most slots (up to 8) that keep the resident
+// workgroups per CU the batch can use.  batch <= 0 assumes a batch much larger than the GPU.
 static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c, std::string &err,
                            int64_t batch = 0)
 {
@@ -819,7 +819,6 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
     const int long_slots = o ? o->long_slots : 0;
     if (long_slots < 0 || long_slots > kMaxLong) { err = "long_slots must be 0..8"; return false; }
     const int nl_max = std::min(kMaxLong, h.n_longp);
-    c.n_long = long_slots ? std::min(long_slots, nl_max) : std::min(2, nl_max);
     const int tile = o ? o->tile : 0, waves = o ? o->waves : 0;
     if (c.precision != PF_FP64 && c.precision != PF_FP32_LU) { err = "unknown precision"; return false; }
     const bool fp64 = c.precision == PF_FP64;
@@ -831,7 +830,11 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
     }
     static const int tiles64[] = {4, 8, 16}, tiles32[] = {8, 16, 32}, wv[] = {2, 4, 8, 16};
     const double b = batch > 0 ? (double)batch : 1e9;
-    struct Cand { int tile, waves, wg; double cost; };
+    auto resident = [&](const Config &k) {
+        const size_t lds = lds_bytes(h, k);
+        return lds > kLdsLimit ? 0 : (int)std::min<size_t>(kLdsLimit / lds, 16 / k.waves);
+    };
+    struct Cand { int tile, waves, n_long, wg; double cost; };
     std::vector<Cand> cands;
     for (const int tc : (fp64 ? tiles64 : tiles32))
         for (const int wc : wv) {
@@ -839,18 +842,29 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
             Config k = c;
             k.tile = tc;
             k.waves = wc;
-            const size_t lds = lds_bytes(h, k);
-            if (lds > kLdsLimit) continue;
-            const int wg = (int)std::max<size_t>(1, std::min<size_t>(kLdsLimit / std::max<size_t>(lds, 1), 16 / wc));
+            k.n_long = long_slots ? std::min(long_slots, nl_max) : std::min(2, nl_max);
+            const int wg0 = resident(k);
+            if (wg0 == 0) continue;
+            if (!long_slots && k.n_long > 0) {
+                const int usable = (int)std::max(1.0, std::ceil(std::ceil(b / tc) / 256.0));
+                const int keep = std::min(wg0, usable);
+                Config m = k;
+                for (int nl = k.n_long + 1; nl <= nl_max; nl++) {
+                    m.n_long = nl;
+                    if (resident(m) >= keep) k.n_long = nl;
+                }
+            }
+            const int wg = std::max(1, resident(k));
             const double gens = std::max(1.0, std::ceil(b / tc) / (256.0 * wg));
-            cands.push_back(Cand{tc, wc, wg, gens / wc * (1.0 + tc / 32.0)});
+            const double slots = k.n_long > 0 ? 0.76 + 0.48 / k.n_long : 1.0;
+            cands.push_back(Cand{tc, wc, k.n_long, wg, gens / wc * (1.0 + tc / 32.0) * slots});
         }
     if (!cands.empty()) {
         double lo = cands[0].cost;
         for (const Cand &k : cands) lo = std::min(lo, k.cost);
         const Cand *pick = nullptr;
         for (const Cand &k : cands) {
-            if (k.cost > lo * 1.1) continue;
+            if (k.cost > lo * 1.03) continue;
             if (!pick) { pick = &k; continue; }
             const bool k8 = k.waves == 8, p8 = pick->waves == 8;
             if (k8 != p8) { if (k8) pick = &k; continue; }
@@ -859,18 +873,7 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
         }
         c.tile = pick->tile;
         c.waves = pick->waves;
-        if (!long_slots && c.n_long > 0) {
-            auto resident = [&](int nl) {
-                Config k = c;
-                k.n_long = nl;
-                const size_t lds = lds_bytes(h, k);
-                return lds > kLdsLimit ? 0 : (int)std::min<size_t>(kLdsLimit / lds, 16 / c.waves);
-            };
-            const int usable = (int)std::max(1.0, std::ceil(std::ceil(b / c.tile) / 256.0));
-            const int keep = std::min(resident(c.n_long), usable);
-            for (int nl = c.n_long + 1; nl <= nl_max; nl++)
-                if (resident(nl) >= keep) c.n_long = nl;
-        }
+        c.n_long = pick->n_long;
         return true;
     }
     err = "the longest LU column (" + std::to_string(h.max_col) + " entries) does not fit in LDS for any "

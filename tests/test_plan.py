@@ -226,22 +226,26 @@ def test_automatic_launch_configuration():
     shapes (many instances of a 1350-bus grid; few of a 9000-bus grid)."""
     g1 = gg.grid("c1_1350bus")
     p1 = pf.Plan.from_ybus(gg.ybus(g1), g1.bus_type)
-    assert (p1.resolve(10000)["tile"], p1.resolve(10000)["waves"]) == (8, 8)
+    assert (p1.resolve(10000)["tile"], p1.resolve(10000)["waves"]) == (8, 16)
     r = p1.resolve(10000, precision=pf.PF_FP32_LU)
-    assert (r["tile"], r["waves"]) == (16, 8)
+    assert (r["tile"], r["waves"]) == (16, 16)
     r = p1.resolve(10000, tile=4, waves=2, schedule=1)
     assert (r["tile"], r["waves"], r["schedule"]) == (4, 2, 1)
     g2 = gg.grid("c2_9000bus")
     p2 = pf.Plan.from_ybus(gg.ybus(g2), g2.bus_type)
     r = p2.resolve(2000)
     assert (r["tile"], r["waves"]) == (8, 16)
-    # long slots: as many as keep the resident workgroups the batch can use (measured:
-    # 1350-bus x 10000 best with 4 at two workgroups per CU; 9000-bus x 2000, one
-    # generation of tiles, takes as many as fit)
-    assert p1.resolve(10000)["long_slots"] == 4
-    assert p1.resolve(10000, precision=pf.PF_FP32_LU)["long_slots"] == 4
+    # long slots: as many as keep the resident workgroups the batch can use.  Measured on
+    # 10,000 scenarios of the 1350-bus grid: FP64 (8, 8) 31.4 / 29.1 / 27.6 ms with 2 / 3 /
+    # 4 slots, (8, 16) with 8 slots 26.2 ms; FP32-LU (16, 8) 23.9 ms, (16, 16) with 8
+    # slots 20.2 ms.  2,000 scenarios of the 9000-bus grid: FP64 (8, 16) 87.2 / 74.8 ms
+    # with 2 / 3 slots (3 is the most that fit), FP32-LU (8, 16) 57.9 / 54.7 ms with 6 / 8.
+    assert p1.resolve(10000)["long_slots"] == 8
+    assert p1.resolve(10000, precision=pf.PF_FP32_LU)["long_slots"] == 8
     assert p2.resolve(2000)["long_slots"] == 3
     assert p2.resolve(2000, precision=pf.PF_FP32_LU)["long_slots"] == 8
+    r = p1.resolve(10000, tile=8, waves=8)
+    assert r["long_slots"] == 4                                  # two workgroups per CU kept
     assert p1.resolve(10000, long_slots=2)["long_slots"] == 2
     g0 = gg.grid("c0_14bus")
     assert pf.Plan.from_ybus(gg.ybus(g0), g0.bus_type).resolve(64)["long_slots"] == 0    # no long panel
