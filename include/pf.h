@@ -132,7 +132,8 @@ size_t pf_workspace_bytes(pf_plan plan, int32_t batch, const pf_solve_opts *opts
 
 /*
  * pf_resolve_opts: the configuration pf_solve_batch would use for batch instances with opts
- * (NULL = defaults): zero tile/waves are replaced by the automatic choice.  PF_EINVAL
+ * (NULL = defaults): zero tile/waves/long_slots are replaced by the automatic choice, and
+ * long_slots is capped at the number of long panels (0 when there are none).  PF_EINVAL
  * for invalid options or when nothing fits in LDS.
  */
 int pf_resolve_opts(pf_plan plan, int32_t batch, const pf_solve_opts *opts, pf_solve_opts *out);
@@ -250,7 +251,9 @@ int pf_mlp_warm_v0(int32_t batch, int32_t n_bus, const float *out, const int32_t
  *
  * pf_queue_create: an empty queue bound to the current device.
  * pf_queue_add: appends one item; arguments as in pf_solve_batch (opts selects precision,
- *   tile, waves and schedule, e.g. from pf_tune).  done_ticks_out [device, may be NULL]
+ *   tile, waves, schedule and long slots, e.g. from pf_tune).  Each item keeps its own
+ *   long-slot count; a group's kernel reserves the largest LDS of its items.
+ *   done_ticks_out [device, may be NULL]
  *   receives, per instance, the device wall-clock ticks from the start of the run to the
  *   moment the instance's results were written (pf_queue_info gives the tick rate).  All
  *   pointers are borrowed: they must stay valid, and keep their addresses, for every
@@ -281,7 +284,8 @@ int pf_queue_info(pf_queue queue, pf_queue_info_t *out);
 void pf_queue_destroy(pf_queue queue);
 
 /*
- * pf_tune: times every configuration (tile, waves, schedule) that fits in LDS on the given
+ * pf_tune: times every configuration (tile, waves, schedule, and long slots: the automatic
+ * count for this batch and 2, 4, 8, each distinct count once) that fits in LDS on the given
  * instances (the same arguments as pf_solve_batch) with reps timed solves after one
  * untimed one, and returns the fastest in best_out (its mean ms per solve in
  * best_ms_out, may be NULL).  waves = 0 tries every workgroup size, otherwise only that

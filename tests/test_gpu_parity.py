@@ -53,7 +53,7 @@ GRIDS_SMALL = ["c0_14bus", "c4_100bus", "c1_1350bus"]
 @pytest.fixture(scope="module")
 def systems():
     out = {}
-    for name in GRIDS_SMALL + ["c2_9000bus"]:
+    for name in GRIDS_SMALL + ["c2_9000bus", "c4_1000bus", "c4_3000bus"]:
         g = gg.grid(name)
         yb = gg.ybus(g)
         out[name] = (g, yb, oracle.System.from_ybus(yb, g.bus_type), pf.Plan.from_ybus(yb, g.bus_type))
@@ -184,6 +184,41 @@ def test_solve_parity_ragged(systems, name, B):
     torch.cuda.synchronize()
     bl = compare_solve(osys, ro, rg)
     assert len(bl) <= B // 20
+
+
+@pytest.mark.parametrize("name,B", [("c4_1000bus", 61), ("c4_3000bus", 37)])
+@pytest.mark.parametrize("prec", [pf.PF_FP64, pf.PF_FP32_LU])
+def test_solve_parity_mid_grids_automatic_configuration(systems, name, B, prec):
+    """The 1000- and 3000-bus grids of the multi-grid workload at their automatic launch
+    configurations (tile 4 or 8, 16 waves, eight long slots), ragged batches.  FP64: the
+    full-solve bar; FP32-LU: converged instances meet the FP64 mismatch test and lie
+    within 1e-6 of the oracle."""
+    g, yb, osys, plan = systems[name]
+    sc = gg.make_scenarios(g, B, 2003, "mc")
+    ro = osys.solve(sc.sbus, sc.v0)
+    y, s, v = to_dev(yb, sc)
+    cfg = plan.resolve(B, precision=prec)
+    print(f"{name} B {B} config {cfg}", flush=True)
+    assert cfg["long_slots"] >= 1
+    rg = pf.solve_batch(plan, y, s, v, precision=prec)
+    torch.cuda.synchronize()
+    if prec == pf.PF_FP64:
+        bl = compare_solve(osys, ro, rg)
+        assert len(bl) <= B // 5                    # most instances get the full comparison
+        vg = rg.v.cpu().numpy()
+        cvg = rg.converged.cpu().numpy().astype(bool)
+        for b in bl:                                # borderline: a converged result is valid
+            if cvg[b]:
+                assert osys.mismatch(sc.sbus[b], vg[b])[1] < 1e-8, b
+    else:
+        cv = rg.converged.cpu().numpy().astype(bool)
+        both = cv & ro.converged
+        assert both.sum() >= 0.95 * ro.converged.sum()
+        vg = rg.v.cpu().numpy()
+        assert np.max(np.abs(vg[both] - ro.v[both])) <= 1e-6
+        for b in np.flatnonzero(both):
+            _, nf = osys.mismatch(sc.sbus[b], vg[b])          # the oracle's FP64 mismatch
+            assert nf < 1e-8, b
 
 
 def test_solve_parity_config1_full_size_sampled(systems):
