@@ -75,7 +75,7 @@ typedef struct {
                               column DAG (default), 1 = elimination order; both are
                               topological, results differ only by rounding order          */
     int32_t long_slots;    /* shared LDS working columns for the panels longer than
-                              info.slot_rows (1..8): more let more of the serial tail of the
+                              info.slot_rows (1..12): more let more of the serial tail of the
                               elimination overlap, at the cost of LDS; 0 = automatic (the
                               most that keep the resident workgroups the batch can use)    */
     int32_t reserved[3];

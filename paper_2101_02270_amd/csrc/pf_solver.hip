@@ -49,7 +49,7 @@ enum Mode { MODE_SOLVE = 0, MODE_MISMATCH = 1, MODE_FACTOR = 2, MODE_STEP = 3 };
 
 constexpr int UPD_GROUP = 3;     // column updates whose operand loads are issued together
 constexpr int L_ROWS = 2;        // rows of each source column per lane loaded with its group
-constexpr int kMaxLong = 8;      // most shared long working-column slots of a launch
+constexpr int kMaxLong = 12;     // most shared long working-column slots of a launch
 
 struct KArgs {
     DevPlan p;
@@ -808,7 +808,7 @@ static constexpr size_t kLdsLimit = 160 * 1024 - 8192;
 // max(1, tiles / resident workgroups) generations, where the resident workgroups per CU are
 // limited by LDS and by the 16 wavefronts per CU that four waves per SIMD allow.  Within 3%
 // of the lowest cost, 8-wave workgroups are preferred, then more resident workgroups.  An
-// automatic L is, for each candidate, the most slots (up to 8) that keep the resident
+// automatic L is, for each candidate, the most slots (up to kMaxLong) that keep the resident
 // workgroups per CU the batch can use.  batch <= 0 assumes a batch much larger than the GPU.
 static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c, std::string &err,
                            int64_t batch = 0)
@@ -817,7 +817,10 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
     c.schedule = o ? o->schedule : 0;
     if (c.schedule != 0 && c.schedule != 1) { err = "schedule must be 0 or 1"; return false; }
     const int long_slots = o ? o->long_slots : 0;
-    if (long_slots < 0 || long_slots > kMaxLong) { err = "long_slots must be 0..8"; return false; }
+    if (long_slots < 0 || long_slots > kMaxLong) {
+        err = "long_slots must be 0.." + std::to_string(kMaxLong);
+        return false;
+    }
     const int nl_max = std::min(kMaxLong, h.n_longp);
     const int tile = o ? o->tile : 0, waves = o ? o->waves : 0;
     if (c.precision != PF_FP64 && c.precision != PF_FP32_LU) { err = "unknown precision"; return false; }

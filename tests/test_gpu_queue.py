@@ -154,7 +154,7 @@ def test_tuner_picks_valid_cached_configuration():
     print(f"\ntuned {best} at {ms:.3f} ms in {t_tune:.2f} s")
     assert best["precision"] == pf.PF_FP64
     assert best["tile"] in (4, 8, 16) and best["waves"] in (2, 4, 8, 16) and best["schedule"] in (0, 1)
-    assert 1 <= best["long_slots"] <= 8                      # the 1000-bus grid has long panels
+    assert 1 <= best["long_slots"] <= 12                     # the 1000-bus grid has long panels
     assert ms > 0
     t0 = time.perf_counter()
     again, ms2 = pf.tune(plan, y, s, v, precision=pf.PF_FP64, reps=1)

@@ -239,17 +239,18 @@ def test_automatic_launch_configuration():
     # 10,000 scenarios of the 1350-bus grid: FP64 (8, 8) 31.4 / 29.1 / 27.6 ms with 2 / 3 /
     # 4 slots, (8, 16) with 8 slots 26.2 ms; FP32-LU (16, 8) 23.9 ms, (16, 16) with 8
     # slots 20.2 ms.  2,000 scenarios of the 9000-bus grid: FP64 (8, 16) 87.2 / 74.8 ms
-    # with 2 / 3 slots (3 is the most that fit), FP32-LU (8, 16) 57.9 / 54.7 ms with 6 / 8.
+    # with 2 / 3 slots (3 is the most that fit), FP32-LU (8, 16) 57.9 / 54.7 / 53.8 / 53.1 ms
+    # with 6 / 8 / 10 / 11 (11 is the most that fit).
     assert p1.resolve(10000)["long_slots"] == 8
     assert p1.resolve(10000, precision=pf.PF_FP32_LU)["long_slots"] == 8
     assert p2.resolve(2000)["long_slots"] == 3
-    assert p2.resolve(2000, precision=pf.PF_FP32_LU)["long_slots"] == 8
+    assert p2.resolve(2000, precision=pf.PF_FP32_LU)["long_slots"] == 11
     r = p1.resolve(10000, tile=8, waves=8)
     assert r["long_slots"] == 4                                  # two workgroups per CU kept
     assert p1.resolve(10000, long_slots=2)["long_slots"] == 2
     g0 = gg.grid("c0_14bus")
     assert pf.Plan.from_ybus(gg.ybus(g0), g0.bus_type).resolve(64)["long_slots"] == 0    # no long panel
-    for bad in (dict(tile=32), dict(waves=3), dict(schedule=2), dict(precision=7), dict(long_slots=9),
+    for bad in (dict(tile=32), dict(waves=3), dict(schedule=2), dict(precision=7), dict(long_slots=13),
                 dict(long_slots=-1)):
         with pytest.raises(pf.PfError):
             p1.resolve(100, **bad)
