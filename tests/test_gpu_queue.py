@@ -167,3 +167,21 @@ def test_tuner_picks_valid_cached_configuration():
     torch.cuda.synchronize()
     assert torch.equal(r.iters, d.iters)
     assert (r.v - d.v).abs().max().item() <= 1e-8
+
+
+def test_queue_group_with_different_long_slot_counts():
+    """Items that share precision, tile and waves form one group whose kernel reserves the
+    largest LDS of its items; each item lays out its own long working-column slots inside
+    it.  Results equal the single-pattern solves with the same options."""
+    q = pf.Queue()
+    _, _, plan, y = system("c1_1350bus")
+    s, v = inputs("c1_1350bus", 24, 31)
+    s2, v2 = inputs("c1_1350bus", 19, 32)
+    a = q.add(plan, y, s, v, precision=pf.PF_FP64, tile=8, waves=8, long_slots=1)
+    b = q.add(plan, y, s2, v2, precision=pf.PF_FP64, tile=8, waves=8, long_slots=6)
+    q.run()
+    torch.cuda.synchronize()
+    assert q.info()["n_groups"] == 1
+    assert_same(a, pf.solve_batch(plan, y, s, v, precision=pf.PF_FP64, tile=8, waves=8, long_slots=1))
+    assert_same(b, pf.solve_batch(plan, y, s2, v2, precision=pf.PF_FP64, tile=8, waves=8, long_slots=6))
+    q.close()
