@@ -250,6 +250,10 @@ def test_automatic_launch_configuration():
     assert p1.resolve(10000, long_slots=2)["long_slots"] == 2
     g0 = gg.grid("c0_14bus")
     assert pf.Plan.from_ybus(gg.ybus(g0), g0.bus_type).resolve(64)["long_slots"] == 0    # no long panel
+    g4 = gg.grid("c4_100bus")
+    p4 = pf.Plan.from_ybus(gg.ybus(g4), g4.bus_type)
+    n_long_panels = int((p4.schedule(0)[2] >= 0).sum())
+    assert p4.resolve(100, long_slots=12)["long_slots"] == min(12, n_long_panels)      # capped
     for bad in (dict(tile=32), dict(waves=3), dict(schedule=2), dict(precision=7), dict(long_slots=13),
                 dict(long_slots=-1)):
         with pytest.raises(pf.PfError):
