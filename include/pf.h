@@ -102,6 +102,14 @@ int pf_analyze(int32_t n_bus, int32_t nnz_y, const int32_t *row_ptr, const int32
 /* Sizes of the plan (host struct). */
 int pf_plan_info(pf_plan plan, pf_plan_info_t *out);
 
+/*
+ * Level histogram of the refactorization's column DAG (Sec. 4.3.1: columns of one level
+ * are independent; few columns per level make the serial region) [host, info.n_levels
+ * entries each]: cols_per_level[l] columns at level l, and madds_per_level[l] (may be NULL)
+ * the multiply-adds of their column updates (their sum is info.flops_refactor).
+ */
+int pf_plan_levels(pf_plan plan, int32_t *cols_per_level, int64_t *madds_per_level);
+
 /* Elimination order [host, N entries]: perm[j] = unknown in position j of A = P J P^T. */
 int pf_plan_order(pf_plan plan, int32_t *perm);
 
@@ -143,7 +151,8 @@ int pf_resolve_opts(pf_plan plan, int32_t batch, const pf_solve_opts *opts, pf_s
  *   ybus [device]      nnz_y complex Ybus values in the pattern's order, shared by every
  *                      instance (ybus_batched = 0), or batch x nnz_y values, one set per
  *                      instance on the same pattern (ybus_batched = 1: N-1 contingency
- *                      cases, where an outaged branch leaves explicit zeros; Sec. 2)
+ *                      cases, where an outaged branch leaves explicit zeros; Sec. 3,
+ *                      the figure of the batched profile data, part c)
  *   sbus [device]      [batch][n_bus] complex specified injections (pu): P at PV and PQ
  *                      buses, Q at PQ buses are used; the rest is ignored
  *   v0 [device]        [batch][n_bus][2] initial (|V|, angle in rad); |V| at PV and REF
@@ -180,9 +189,9 @@ int pf_solve_batch(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus
  * an in-kernel fallback: an instance whose attempt from v0 fails (non-finite mismatch, an
  * update that does not reduce max|F|, or a zero pivot) restarts once from v_fallback
  * [device, B x n_bus x 2, same layout as v0; typically the flat start].  max_iter bounds
- * the voltage updates of both attempts together, so a restarted instance never runs
- * longer than a plain solve could; iters_out counts those updates; status and converged
- * describe the final attempt.
+ * the voltage updates of each attempt, so the restart runs exactly as a plain solve from
+ * v_fallback would (every instance that solve converges also converges here); iters_out
+ * counts the updates of both attempts; status and converged describe the final attempt.
  * Other arguments and errors as pf_solve_batch.
  */
 int pf_solve_batch_warm(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus_batched,
@@ -287,12 +296,13 @@ void pf_queue_destroy(pf_queue queue);
  * pf_tune: times every configuration (tile, waves, schedule, and long slots: the automatic
  * count for this batch and 2, 4, 8, each distinct count once) that fits in LDS on the given
  * instances (the same arguments as pf_solve_batch) with reps timed solves after one
- * untimed one, and returns the fastest in best_out (its mean ms per solve in
- * best_ms_out, may be NULL).  waves = 0 tries every workgroup size, otherwise only that
- * one.  Results are cached in
- * the process, keyed by the plan's pattern hash, device, precision, waves and batch;
- * flags & PF_TUNE_FORCE re-times a cached key.  Allocates and frees its own device
- * buffers; synchronises with stream.
+ * untimed one, and returns the one with the most converged flows per second in best_out
+ * (its mean ms per solve in best_ms_out, may be NULL).  A candidate whose untimed solve
+ * converges fewer instances than the default configuration's, or reports PF_ST_INTERNAL,
+ * is not timed.  waves = 0 tries every workgroup size, otherwise only that one.  Results
+ * are cached in the process, keyed by the plan's pattern hash, device, precision, waves,
+ * batch, tol and max_iter; flags & PF_TUNE_FORCE re-times a cached key.  Allocates and
+ * frees its own device buffers; synchronises with stream.
  */
 enum { PF_TUNE_FORCE = 1 };
 int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus, const double *v0, double tol,
@@ -329,6 +339,25 @@ int pf_branch_flows(int32_t n_bus, int32_t n_branch, const int32_t *from_bus, co
 int pf_solve_host(pf_plan plan, int32_t batch, const double *ybus, const double *sbus_host, const double *v0_host,
                   double tol, int32_t max_iter, const pf_solve_opts *opts, int32_t chunk, double *v_out_host,
                   int32_t *iters_host, uint8_t *converged_host, int8_t *status_host, void *stream);
+
+/*
+ * pf_cpu_solve_batch: the batched CPU engine (Sec. 4.2, Alg. 2 run over mini-batches; Sec.
+ * 3.1): the same Newton iterations as pf_solve_batch in FP64 on the host, with the plan's
+ * pre-order, pattern and update lists.  The batch is cut into mini-batches of 8 instances
+ * stored side by side ([element][8]), so every inner loop is a SIMD operation over the
+ * mini-batch (AVX-512, AVX2 or plain code, chosen at run time for the host CPU), and
+ * `threads` worker threads (0 = every online core) take mini-batches from a shared
+ * counter.  A separate engine for CPU hosts and a baseline for the GPU path: no GPU entry
+ * point calls it.
+ *   ybus [host]    nnz_y complex values (shared by the batch)
+ *   sbus, v0 [host], v_out [host], iters_out, converged_out, status_out (may be NULL)
+ *   [host]         as pf_solve_batch
+ * Synchronous; needs no device.  PF_EINVAL for invalid arguments, PF_ENOMEM when a
+ * thread's scratch (about 16 (nnz_lu + 6 n) * 8 bytes) cannot be allocated.
+ */
+int pf_cpu_solve_batch(pf_plan plan, int32_t batch, const double *ybus, const double *sbus, const double *v0,
+                       double tol, int32_t max_iter, int32_t threads, double *v_out, int32_t *iters_out,
+                       uint8_t *converged_out, int8_t *status_out);
 
 /* Release the plan and its device memory. */
 void pf_plan_destroy(pf_plan plan);

@@ -28,7 +28,8 @@ EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
             "pf_mlp_act_backward", "pf_mlp_mse", "pf_mlp_adam", "pf_mlp_to_bf16",
             "pf_mlp_features", "pf_mlp_warm_v0", "pf_queue_create", "pf_queue_add",
             "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune", "pf_solve_batch_warm",
-            "pf_resolve_opts", "pf_branch_flows", "pf_plan_schedule", "pf_solve_host"]
+            "pf_resolve_opts", "pf_branch_flows", "pf_plan_schedule", "pf_solve_host",
+            "pf_plan_levels", "pf_cpu_solve_batch"]
 
 
 class PfError(RuntimeError):
@@ -76,6 +77,9 @@ def lib():
                                  _i32p, ctypes.POINTER(_vp)]
         L.pf_plan_info.argtypes = [_vp, ctypes.POINTER(_PlanInfo)]
         L.pf_plan_order.argtypes = [_vp, _i32p]
+        L.pf_plan_levels.argtypes = [_vp, _i32p, ctypes.POINTER(ctypes.c_int64)]
+        L.pf_cpu_solve_batch.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
+                                         ctypes.c_int32, _vp, _vp, _vp, _vp]
         L.pf_plan_lu_pattern.argtypes = [_vp, _i32p, _i32p, _i32p]
         L.pf_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_Opts)]
         L.pf_workspace_bytes.restype = ctypes.c_size_t
@@ -173,6 +177,15 @@ class Plan:
         p = np.zeros(self.N, np.int32)
         _check(lib().pf_plan_order(self._h, p.ctypes.data_as(_i32p)), "pf_plan_order")
         return p
+
+    def levels(self):
+        """(columns per level, multiply-adds per level) of the refactorization's column DAG."""
+        nl = self.info["n_levels"]
+        cols = np.zeros(nl, np.int32)
+        madds = np.zeros(nl, np.int64)
+        _check(lib().pf_plan_levels(self._h, cols.ctypes.data_as(_i32p),
+                                    madds.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), "pf_plan_levels")
+        return cols, madds
 
     def lu_pattern(self):
         cp = np.zeros(self.N + 1, np.int32)
@@ -469,4 +482,35 @@ def solve_host(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10
                              _vp(out.iters.data_ptr()), _vp(out.converged.data_ptr()), _vp(out.status.data_ptr()),
                              _stream_ptr(stream))
     _check(rc, "pf_solve_host")
+    return out
+
+
+@dataclass
+class HostResult:
+    v: np.ndarray          # float64 [B][n][2]
+    iters: np.ndarray      # int32 [B]
+    converged: np.ndarray  # bool [B]
+    status: np.ndarray     # int8 [B]
+
+
+def cpu_solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
+                    threads: int = 0) -> HostResult:
+    """pf_cpu_solve_batch on host arrays: ybus complex128 [nnz_y], sbus complex128 [B][n],
+    v0 float64 [B][n][2].  The batched CPU engine (mini-batches of 8 in SIMD lanes, worker
+    threads over mini-batches; threads = 0 uses every online core).  It is a separate
+    engine, not a fallback of the GPU entry points."""
+    y = np.ascontiguousarray(np.asarray(ybus, dtype=np.complex128)).view(np.float64)
+    s = np.ascontiguousarray(np.asarray(sbus, dtype=np.complex128)).view(np.float64)
+    v = np.ascontiguousarray(v0, dtype=np.float64)
+    B = int(v.shape[0])
+    if y.shape[0] != 2 * plan.nnz_y or s.shape != (B, 2 * plan.n) or v.shape != (B, plan.n, 2):
+        raise PfError("ybus, sbus or v0 has the wrong shape for this plan")
+    out = HostResult(v=np.empty((B, plan.n, 2)), iters=np.empty(B, np.int32),
+                     converged=np.empty(B, np.uint8), status=np.empty(B, np.int8))
+    rc = lib().pf_cpu_solve_batch(plan._h, B, _vp(y.ctypes.data), _vp(s.ctypes.data), _vp(v.ctypes.data),
+                                  float(tol), int(max_iter), int(threads), _vp(out.v.ctypes.data),
+                                  _vp(out.iters.ctypes.data), _vp(out.converged.ctypes.data),
+                                  _vp(out.status.ctypes.data))
+    _check(rc, "pf_cpu_solve_batch")
+    out.converged = out.converged.astype(bool)
     return out

@@ -8,6 +8,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpf_hip.so")
 SOURCES = ["pf_solver.hip", "pf_plan.cpp", "pf_mlp.hip", "pf_flows.hip", "pf_host.cpp"]
+# host-only sources compiled by the system C++ compiler (vectorised CPU engine) and linked in
+CPU_SOURCES = ["pf_cpu.cpp"]
+CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fno-math-errno", "-pthread"]
+OBJ_DIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -24,9 +28,21 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    objs = []
+    for src in CPU_SOURCES:
+        obj = os.path.join(OBJ_DIR, os.path.splitext(src)[0] + ".o")
+        cmd = ["g++", *CXX_FLAGS, "-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("g++ failed:\n" + res.stdout + res.stderr)
+        objs.append(obj)
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, *srcs]
+    # "-x none": the objects follow sources that hipcc marks "-x hip"
+    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, *srcs, "-x", "none", *objs, "-pthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -1,6 +1,6 @@
-// Branch power flows and losses at solved voltages: the post-processing of a power flow
-// (the quantities the scenarios are run for; Sec. 1-2).  Pi-model branches with series
-// admittance y = 1/(r + jx) and total charging b split b/2 per end:
+// Branch power flows and losses at solved voltages: the post-processing step that follows
+// the final convergence check, computed in parallel over instances (Sec. 3.2).  Pi-model
+// branches with series admittance y = 1/(r + jx) and total charging b split b/2 per end:
 //   I_from = y (V_from - V_to) + j b/2 V_from,   S_from = V_from conj(I_from)
 //   I_to   = y (V_to - V_from) + j b/2 V_to,     S_to   = V_to conj(I_to)
 // and the instance's losses are the sum over branches of S_from + S_to.

@@ -1,7 +1,8 @@
 // Solve of a host-resident batch with transfers overlapped with compute: the batch is cut
 // into chunks, and two streams alternate copy-in, solve and copy-out, so chunk i+1's
 // inputs travel over PCIe while chunk i is solved (the paper overlaps its host-device
-// transfers the same way, Sec. 4).  Built on the public entry points.
+// transfers with kernels through streams, Sec. 2.2 and Sec. 5.3).  Built on the public
+// entry points.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

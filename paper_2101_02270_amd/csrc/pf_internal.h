@@ -130,4 +130,9 @@ int analyze(int n, int nnzy, const int32_t *row_ptr, const int32_t *col_idx,
 
 void set_error(const std::string &msg);
 
+// batched CPU engine (pf_cpu.cpp): host arrays, threads = 0 uses every online core
+int cpu_solve(const HostPlan &h, int32_t batch, const double *ybus, const double *sbus, const double *v0, double tol,
+              int32_t max_iter, int32_t threads, double *v_out, int32_t *iters_out, uint8_t *conv_out,
+              int8_t *status_out, std::string &err);
+
 }  // namespace pf

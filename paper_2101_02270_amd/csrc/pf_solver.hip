@@ -95,43 +95,78 @@ __device__ __forceinline__ void wave_sync()
 // makes its global writes visible to the workgroup (release fence) and then every lane of
 // the wavefront stores the same flag byte (plain stores, no atomics, so the loops stay free
 // of lane-divergent regions).  A consumer polls the byte uniformly across the wavefront
-// and acquires.  Every wait is bounded: a wait that exceeds the limit raises the tile's
-// error flag and stops waiting, so a wrong schedule can only produce wrong numbers and an
-// error status, never a hang.
-__device__ __forceinline__ void wait_published(unsigned char *flags, int j, int *err)
+// and acquires.
+//
+// Every wait is bounded by progress, not by time: each wavefront counts its own
+// publications in an LDS word (only that wavefront writes it, so plain stores suffice), and
+// a waiter restarts its poll count whenever the sum over the workgroup's wavefronts has
+// moved.  Only kNoProgressPolls polls in a row with no publication anywhere in the
+// workgroup (about 0.1 s; a panel publishes within microseconds) raise the tile's error
+// flag and end the wait, so a wrong schedule can only produce an error status, never a
+// hang, while a slow but progressing tile always completes.
+constexpr unsigned kNoProgressPolls = 1u << 22;
+constexpr unsigned kProgressCheck = 256;       // polls between reads of the progress words
+
+template <int NW>
+__device__ __forceinline__ int progress_sum(const int *prog)
 {
-    for (unsigned spins = 0;; ++spins) {
+    int s = 0;
+#pragma unroll
+    for (int w = 0; w < NW; w++) s += __hip_atomic_load(&prog[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return __builtin_amdgcn_readfirstlane(s);
+}
+
+// The slow path of a wait: called after a poll found the condition unmet.  Returns true
+// when the wait must end (error raised here or by another wavefront).
+template <int NW>
+__device__ __forceinline__ bool wait_tick(unsigned &spins, int &seen, const int *prog, int *err)
+{
+    const int e = __builtin_amdgcn_readfirstlane(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+    if (e) return true;
+    if ((++spins & (kProgressCheck - 1)) == 0) {
+        const int now = progress_sum<NW>(prog);
+        if (now != seen) {
+            seen = now;
+            spins = 0;
+        } else if (spins >= kNoProgressPolls) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return true;
+        }
+    }
+    __builtin_amdgcn_s_sleep(1);
+    return false;
+}
+
+template <int NW>
+__device__ __forceinline__ void wait_published(unsigned char *flags, int j, const int *prog, int *err)
+{
+    unsigned spins = 0;
+    int seen = -1;
+    for (;;) {
         const int f = __builtin_amdgcn_readfirstlane(
             (int)__hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-        if (f) break;
-        const int e = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-        if (e) break;
-        if (spins >= (1u << 22)) {
-            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+        if (f || wait_tick<NW>(spins, seen, prog, err)) break;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// The same bounded wait for an LDS counter to reach a value (counters only grow).
-__device__ __forceinline__ void wait_count(int *ctr, int target, int *err)
+// The same wait for an LDS counter to reach a value (counters only grow).
+template <int NW>
+__device__ __forceinline__ void wait_count(int *ctr, int target, const int *prog, int *err)
 {
-    for (unsigned spins = 0;; ++spins) {
+    unsigned spins = 0;
+    int seen = -1;
+    for (;;) {
         const int v = __builtin_amdgcn_readfirstlane(__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-        if (v >= target) break;
-        const int e = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-        if (e) break;
-        if (spins >= (1u << 22)) {
-            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+        if (v >= target || wait_tick<NW>(spins, seen, prog, err)) break;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// A wavefront records one more publication in its progress word.
+__device__ __forceinline__ void note_progress(int *prog, int wave, int &count)
+{
+    __hip_atomic_store(&prog[wave], ++count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // The whole Newton loop of one tile (T instances) by one workgroup.  Called by the
@@ -148,11 +183,12 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     __shared__ double s_red[NW][T];
     __shared__ int s_bad[NW][T];
     __shared__ int s_active[T], s_status[T], s_iters[T], s_piv[T];
-    __shared__ int s_retry[T], s_reset[T], s_nupd[T];
+    __shared__ int s_retry[T], s_reset[T], s_nupd[T], s_base[T];
     __shared__ double s_prevf[T];
     __shared__ double s_normf[T];
     __shared__ int s_any, s_err;
     __shared__ int s_lgen[kMaxLong];    // publications seen by each long working-column slot
+    __shared__ int s_prog[NW];          // publications made by each wavefront (progress bound)
 
     const DevPlan &P = a.p;
     const int tid = threadIdx.x;
@@ -186,6 +222,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     unsigned char *done = reinterpret_cast<unsigned char *>(
         long_base + (size_t)a.n_long * 2 * P.max_col * T + (size_t)NW * 2 * T);
     int *err = &s_err;
+    int nprog = 0;                      // this wavefront's publications so far
 
     // ---- boundary layout [B][n][2] -> tile layout [n][T]
     for (int i = slot; i < n; i += SLOTS) {
@@ -202,10 +239,11 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         s_active[t] = valid ? 1 : 0;
         s_status[t] = PF_ST_MAXITER;
         s_iters[t] = 0;
-        s_retry[t] = 0; s_reset[t] = 0; s_nupd[t] = 0;
+        s_retry[t] = 0; s_reset[t] = 0; s_nupd[t] = 0; s_base[t] = 0;
         s_prevf[t] = INFINITY;
     }
     if (tid == 0) s_err = 0;
+    if (tid < NW) s_prog[tid] = 0;
     __syncthreads();
 
     for (int it = 0;; ++it) {
@@ -302,18 +340,19 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             s_normf[t] = nb ? NAN : nf;
             s_piv[t] = 0;
             if (s_active[t] && a.mode == MODE_SOLVE) {
-                // iters counts voltage updates; max_iter bounds them over both attempts (a
-                // plain solve updates once per iteration, so this is its iteration bound)
+                // iters counts voltage updates over both attempts; max_iter bounds the
+                // updates of each attempt (s_base: the count when the current one began), so
+                // a restart from the fallback point runs exactly as a plain solve from there
                 int fail = 0;
                 if (nb) fail = PF_ST_NONFINITE;
                 else if (nf < a.tol) { s_status[t] = PF_ST_CONVERGED; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
-                else if (s_nupd[t] >= a.max_iter) fail = PF_ST_MAXITER;
+                else if (s_nupd[t] - s_base[t] >= a.max_iter) fail = PF_ST_MAXITER;
                 // an attempt that has a fallback gives up as soon as an update fails to
                 // reduce the mismatch (Newton from a good start contracts every step)
                 else if (a.v_fb && !s_retry[t] && !(nf < s_prevf[t])) fail = PF_ST_MAXITER;
                 s_prevf[t] = nf;
                 if (fail) {
-                    if (a.v_fb && !s_retry[t] && s_nupd[t] < a.max_iter) { s_retry[t] = 1; s_reset[t] = 1; }
+                    if (a.v_fb && !s_retry[t]) { s_retry[t] = 1; s_reset[t] = 1; s_base[t] = s_nupd[t]; }
                     else { s_status[t] = fail; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
                 }
             }
@@ -333,9 +372,9 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             if (a.mode != MODE_SOLVE) return;
             break;
         }
-        // every instance ends within max_iter + 3 passes (updates over both attempts, the
-        // restart pass and the final test); a tile still running well past that has lost
-        // its state and reports an internal error instead of looping on
+        // every instance ends within 2 max_iter + 3 passes (the updates of both attempts,
+        // the restart pass and the final tests); a tile still running well past that has
+        // lost its state and reports an internal error instead of looping on
         if (it > 2 * a.max_iter + 4) {
             if (tid == 0) s_err = 1;
             __syncthreads();
@@ -428,7 +467,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 xw = short_base + (size_t)wave * 2 * P.slot_rows * T;
                 xw1 = xw + (size_t)P.slot_rows * T;
             } else {
-                if (lgen > 0) wait_count(&s_lgen[lslot], lgen, err);
+                if (lgen > 0) wait_count<NW>(&s_lgen[lslot], lgen, s_prog, err);
                 xw = long_base + (size_t)lslot * 2 * P.max_col * T;
                 xw1 = xw + (size_t)P.max_col * T;
             }
@@ -485,7 +524,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 }
                 Update ups[UPD_GROUP];
                 ups[0] = upd_rec(ub);
-                wait_published(done, ups[0].k, err);
+                wait_published<NW>(done, ups[0].k, s_prog, err);
                 int gcnt = 1;
 #pragma unroll
                 for (int g = 1; g < UPD_GROUP; g++) {
@@ -579,10 +618,11 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             __hip_atomic_store(&done[j], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (two) __hip_atomic_store(&done[j + 1], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (lslot >= 0) __hip_atomic_store(&s_lgen[lslot], lgen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            note_progress(s_prog, wave, nprog);
         }
         __syncthreads();
         if (tid < T && s_piv[t] && s_active[t] && !s_reset[t] && a.mode == MODE_SOLVE) {
-            if (a.v_fb && !s_retry[t]) { s_retry[t] = 1; s_reset[t] = 1; }
+            if (a.v_fb && !s_retry[t]) { s_retry[t] = 1; s_reset[t] = 1; s_base[t] = s_nupd[t]; }
             else { s_status[t] = PF_ST_PIVOT; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
         }
         if (a.mode == MODE_FACTOR) {
@@ -664,17 +704,11 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                     const bool in = q < q1;
                     const int c = in ? c_all : -1;
                     const int pq = in ? pq_all : 1;
-                    for (unsigned spins = 0;; ++spins) {
+                    unsigned spins = 0;
+                    int seen = -1;
+                    for (;;) {
                         const bool ok = c < 0 || __hip_atomic_load(&done[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        if (__all(ok)) break;
-                        const int e = __builtin_amdgcn_readfirstlane(
-                            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-                        if (e) break;
-                        if (spins >= (1u << 22)) {
-                            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
+                        if (__all(ok) || wait_tick<NW>(spins, seen, s_prog, err)) break;
                     }
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                     const R z = Yv[(in ? c : j) * T + t];
@@ -698,17 +732,11 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                     const int c_all = P.bs_col[q], pq_all = P.bs_pos[q];   // padded tables
                     const int c = in ? c_all : -1;
                     const int pq = in ? pq_all : 1;
-                    for (unsigned spins = 0;; ++spins) {
+                    unsigned spins = 0;
+                    int seen = -1;
+                    for (;;) {
                         const bool ok = c < 0 || __hip_atomic_load(&done[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        if (__all(ok)) break;
-                        const int e = __builtin_amdgcn_readfirstlane(
-                            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-                        if (e) break;
-                        if (spins >= (1u << 22)) {
-                            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
+                        if (__all(ok) || wait_tick<NW>(spins, seen, s_prog, err)) break;
                     }
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                     const R z = Yv[(in ? c : j) * T + t];
@@ -754,6 +782,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __hip_atomic_store(&done[j], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (two) __hip_atomic_store(&done[j + 1], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            note_progress(s_prog, wave, nprog);
         }
         __syncthreads();
         if (a.mode == MODE_STEP) {
@@ -1384,10 +1413,12 @@ static int queue_build(Queue *q)
 // ------------------------------------------------------------------ autotuner
 struct TuneKey {
     uint64_t hash;
-    int device, precision, waves, batch;
+    int device, precision, waves, batch, max_iter;
+    double tol;
     bool operator<(const TuneKey &o) const
     {
-        return std::tie(hash, device, precision, waves, batch) < std::tie(o.hash, o.device, o.precision, o.waves, o.batch);
+        return std::tie(hash, device, precision, waves, batch, max_iter, tol) <
+               std::tie(o.hash, o.device, o.precision, o.waves, o.batch, o.max_iter, o.tol);
     }
 };
 static std::mutex g_tune_mu;
@@ -1458,6 +1489,24 @@ int pf_plan_info(pf_plan plan, pf_plan_info_t *o)
     o->bytes_iter_fp64 = 4 * 8 * (int64_t)o->nnz_lu + 80 * (int64_t)h.n + 32 * (int64_t)h.N;
     o->bytes_iter_fp32 = 4 * 4 * (int64_t)o->nnz_lu + 80 * (int64_t)h.n + 32 * (int64_t)h.N;
     o->pattern_hash = pattern_hash(h);
+    return PF_OK;
+}
+
+int pf_plan_levels(pf_plan plan, int32_t *cols_per_level, int64_t *madds_per_level)
+{
+    Plan *pl = reinterpret_cast<Plan *>(plan);
+    if (!pl || !cols_per_level) { set_error("null argument"); return PF_EINVAL; }
+    const HostPlan &h = pl->h;
+    const int nlev = (int)h.lev_ptr.size() - 1;
+    for (int l = 0; l < nlev; l++) cols_per_level[l] = h.lev_ptr[l + 1] - h.lev_ptr[l];
+    if (madds_per_level) {
+        for (int l = 0; l < nlev; l++) madds_per_level[l] = 0;
+        for (int j = 0; j < h.N; j++) {
+            int64_t w = 0;
+            for (int u = h.upd_ptr[j]; u < h.upd_ptr[j + 1]; u++) w += h.upd[u].krel_lcnt >> 16;
+            madds_per_level[h.level[j]] += w;
+        }
+    }
     return PF_OK;
 }
 
@@ -1689,7 +1738,7 @@ int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
         set_error("the current device differs from the plan's device");
         return PF_EDEVICE;
     }
-    const TuneKey key{pattern_hash(pl->h), dev, precision, waves, batch};
+    const TuneKey key{pattern_hash(pl->h), dev, precision, waves, batch, max_iter, tol};
     if (!(flags & PF_TUNE_FORCE)) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto f = g_tune_cache.find(key);
@@ -1746,9 +1795,32 @@ int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = PF_OK;
-    double best = 1e300;
+    // candidates are scored by converged flows per millisecond; one that converges fewer
+    // instances than the default configuration, or reports an internal error, is rejected
+    std::vector<int8_t> h_st((size_t)batch);
+    auto outcome = [&](int &nconv, int &nint) -> int {
+        if (hipMemcpyAsync(h_st.data(), st_out, (size_t)batch, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            set_error("tuning run failed");
+            return PF_EDEVICE;
+        }
+        nconv = 0; nint = 0;
+        for (const int8_t x : h_st) { nconv += x == PF_ST_CONVERGED; nint += x == PF_ST_INTERNAL; }
+        return PF_OK;
+    };
+    int ref_conv = -1;
+    {
+        pf_solve_opts d{};
+        d.precision = precision;
+        d.waves = waves;
+        rc = pf_solve_batch(plan, batch, ybus, 0, sbus, v0, tol, max_iter, &d, m, ws, v_out, it_out, cv_out, st_out,
+                            stream);
+        int ni = 0;
+        if (rc == PF_OK) rc = outcome(ref_conv, ni);
+    }
+    double best = -1.0, best_ms = 0.0;
     pf_solve_opts best_o = cand[0];
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (rc == PF_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
         set_error("event creation failed");
         rc = PF_EDEVICE;
     }
@@ -1757,6 +1829,9 @@ int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
         rc = pf_solve_batch(plan, batch, ybus, 0, sbus, v0, tol, max_iter, &o, m, ws, v_out, it_out, cv_out, st_out,
                             stream);
         if (rc != PF_OK) break;
+        int nconv = 0, nint = 0;
+        if ((rc = outcome(nconv, nint)) != PF_OK) break;
+        if (nint > 0 || nconv < ref_conv) continue;
         (void)hipEventRecord(e0, st);
         for (int r = 0; r < reps && rc == PF_OK; r++)
             rc = pf_solve_batch(plan, batch, ybus, 0, sbus, v0, tol, max_iter, &o, m, ws, v_out, it_out, cv_out,
@@ -1766,7 +1841,12 @@ int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
         const double per = ms / reps;
-        if (per < best) { best = per; best_o = o; }
+        const double score = per > 0.0 ? nconv / per : 0.0;
+        if (score > best) { best = score; best_ms = per; best_o = o; }
+    }
+    if (rc == PF_OK && best < 0.0) {
+        set_error("no candidate configuration matched the default configuration's converged count");
+        rc = PF_EINVAL;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -1774,11 +1854,28 @@ int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
     if (rc != PF_OK) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[key] = {best_o, best};
+        g_tune_cache[key] = {best_o, best_ms};
     }
     *best_out = best_o;
-    if (best_ms_out) *best_ms_out = best;
+    if (best_ms_out) *best_ms_out = best_ms;
     return PF_OK;
+}
+
+int pf_cpu_solve_batch(pf_plan plan, int32_t batch, const double *ybus, const double *sbus, const double *v0,
+                       double tol, int32_t max_iter, int32_t threads, double *v_out, int32_t *iters_out,
+                       uint8_t *converged_out, int8_t *status_out)
+{
+    Plan *pl = reinterpret_cast<Plan *>(plan);
+    if (!pl) { set_error("null plan"); return PF_EINVAL; }
+    if (batch < 0 || threads < 0) { set_error("negative batch or thread count"); return PF_EINVAL; }
+    if (batch == 0) return PF_OK;
+    if (!ybus || !sbus || !v0 || !v_out || !iters_out || !converged_out) { set_error("null pointer"); return PF_EINVAL; }
+    if (max_iter < 0 || !(tol >= 0.0)) { set_error("invalid tol or max_iter"); return PF_EINVAL; }
+    std::string err;
+    const int rc = cpu_solve(pl->h, batch, ybus, sbus, v0, tol, max_iter, threads, v_out, iters_out, converged_out,
+                             status_out, err);
+    if (rc != PF_OK) set_error(err);
+    return rc;
 }
 
 void pf_plan_destroy(pf_plan plan)

@@ -230,18 +230,36 @@ class WarmStartNet:
         return v0
 
     def save(self, path):
-        np.savez(path, dims=np.array(self.dims), feat_bus=self.feat_bus,
-                 **{f"W{l}": w.cpu().numpy() for l, w in enumerate(self.W)},
-                 **{f"b{l}": b.cpu().numpy() for l, b in enumerate(self.b)},
+        """Checkpoint: FP32 master weights and biases, the Adam moments and step count (so
+        training resumes where it stopped), and the normalisation constants."""
+        arrs = {}
+        for l in range(len(self.W)):
+            arrs[f"W{l}"] = self.W[l].cpu().numpy()
+            arrs[f"b{l}"] = self.b[l].cpu().numpy()
+            arrs[f"mW{l}"] = self.mW[l].cpu().numpy()
+            arrs[f"vW{l}"] = self.vW[l].cpu().numpy()
+            arrs[f"mb{l}"] = self.mb[l].cpu().numpy()
+            arrs[f"vb{l}"] = self.vb[l].cpu().numpy()
+        np.savez(path, dims=np.array(self.dims), feat_bus=self.feat_bus, adam_step=np.array(self.step),
                  mu_x=self.mu_x.cpu().numpy(), sd_x=self.sd_x.cpu().numpy(),
-                 mu_y=self.mu_y.cpu().numpy(), sd_y=self.sd_y.cpu().numpy())
+                 mu_y=self.mu_y.cpu().numpy(), sd_y=self.sd_y.cpu().numpy(), **arrs)
 
     def load(self, path):
-        d = np.load(path)
+        """Restores a checkpoint written by save() into a network of the same shape; plain
+        arrays only (no pickled objects are read)."""
+        d = np.load(path, allow_pickle=False)
+        if list(d["dims"]) != list(self.dims):
+            raise PfError(f"checkpoint dims {list(d['dims'])} differ from the network's {self.dims}")
         t = self.torch
         for l in range(len(self.W)):
             self.W[l].copy_(t.from_numpy(d[f"W{l}"]))
             self.b[l].copy_(t.from_numpy(d[f"b{l}"]))
+            if f"mW{l}" in d:
+                self.mW[l].copy_(t.from_numpy(d[f"mW{l}"]))
+                self.vW[l].copy_(t.from_numpy(d[f"vW{l}"]))
+                self.mb[l].copy_(t.from_numpy(d[f"mb{l}"]))
+                self.vb[l].copy_(t.from_numpy(d[f"vb{l}"]))
+        self.step = int(d["adam_step"]) if "adam_step" in d else 0
         self._refresh_bf16()
         self.set_normalization(d["mu_x"], d["sd_x"], d["mu_y"], d["sd_y"])
 

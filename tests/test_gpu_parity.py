@@ -9,8 +9,10 @@ Bars (spec tolerances, written out here):
     counts and convergence flags (instances whose final or penultimate mismatch lies
     within a factor 2 of the tolerance in either implementation are reported as
     borderline and only need both results to be valid);
-  * FP32-LU: converged instances meet the same FP64 mismatch test and are within 1e-6 of
-    the oracle; extra iterations are reported, not bounded (no paper figure exists).
+  * FP32-LU: every instance the oracle converges converges; converged instances meet the
+    oracle's FP64 mismatch test at the returned V and are within 1e-6 of the oracle; extra
+    iterations are reported and bounded by 2 (no paper figure exists);
+  * no instance of any solve reports PF_ST_INTERNAL (the dataflow waits end by progress).
 """
 import os
 
@@ -27,6 +29,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_2101_02270_amd as pf  # noqa: E402
+from tests.parity import compare_fp32lu, compare_solve  # noqa: E402
 
 DEV = "cuda"
 
@@ -142,26 +145,6 @@ def test_newton_step_residual(systems, name):
 
 
 # ----------------------------------------------------------------- full solve parity
-def compare_solve(osys, res_o, res_g, tol=1e-8, vtol=1e-6):
-    v_g = res_g.v.cpu().numpy(); it_g = res_g.iters.cpu().numpy()
-    cv_g = res_g.converged.cpu().numpy().astype(bool); st_g = res_g.status.cpu().numpy()
-    borderline = []
-    for b in range(v_g.shape[0]):
-        h = res_o.hist[b]
-        k = res_o.iters[b]
-        near = any(0.5 * tol <= x <= 2 * tol for x in h[max(0, k - 1):k + 1] if np.isfinite(x))
-        if near:
-            borderline.append(b)
-            continue
-        assert cv_g[b] == res_o.converged[b], (b, st_g[b], res_o.status[b])
-        if res_o.converged[b]:
-            assert it_g[b] == res_o.iters[b], (b, it_g[b], res_o.iters[b])
-            assert np.max(np.abs(v_g[b, :, 0] - res_o.v[b, :, 0])) <= vtol
-            assert np.max(np.abs(v_g[b, :, 1] - res_o.v[b, :, 1])) <= vtol
-            assert st_g[b] == pf.PF_ST_CONVERGED
-    return borderline
-
-
 @pytest.mark.parametrize("tile,waves", [(8, 4), (16, 4), (16, 2), (16, 8)])
 def test_solve_config0_full(systems, tile, waves):
     g, yb, osys, plan = systems["c0_14bus"]
@@ -170,7 +153,7 @@ def test_solve_config0_full(systems, tile, waves):
     y, s, v = to_dev(yb, sc)
     rg = pf.solve_batch(plan, y, s, v, tile=tile, waves=waves)
     torch.cuda.synchronize()
-    compare_solve(osys, ro, rg)
+    compare_solve(osys, ro, rg, sc.sbus)
     assert rg.converged.cpu().numpy().all()
 
 
@@ -182,7 +165,7 @@ def test_solve_parity_ragged(systems, name, B):
     y, s, v = to_dev(yb, sc)
     rg = pf.solve_batch(plan, y, s, v)
     torch.cuda.synchronize()
-    bl = compare_solve(osys, ro, rg)
+    bl = compare_solve(osys, ro, rg, sc.sbus)
     assert len(bl) <= B // 20
 
 
@@ -203,61 +186,58 @@ def test_solve_parity_mid_grids_automatic_configuration(systems, name, B, prec):
     rg = pf.solve_batch(plan, y, s, v, precision=prec)
     torch.cuda.synchronize()
     if prec == pf.PF_FP64:
-        bl = compare_solve(osys, ro, rg)
+        bl = compare_solve(osys, ro, rg, sc.sbus)
         assert len(bl) <= B // 5                    # most instances get the full comparison
-        vg = rg.v.cpu().numpy()
-        cvg = rg.converged.cpu().numpy().astype(bool)
-        for b in bl:                                # borderline: a converged result is valid
-            if cvg[b]:
-                assert osys.mismatch(sc.sbus[b], vg[b])[1] < 1e-8, b
     else:
-        cv = rg.converged.cpu().numpy().astype(bool)
-        both = cv & ro.converged
-        assert both.sum() >= 0.95 * ro.converged.sum()
-        vg = rg.v.cpu().numpy()
-        assert np.max(np.abs(vg[both] - ro.v[both])) <= 1e-6
-        for b in np.flatnonzero(both):
-            _, nf = osys.mismatch(sc.sbus[b], vg[b])          # the oracle's FP64 mismatch
-            assert nf < 1e-8, b
+        compare_fp32lu(osys, ro, rg, sc.sbus, name=name)
 
 
-def test_solve_parity_config1_full_size_sampled(systems):
-    """10,000 instances in the benchmark's launch configuration; 120 sampled instances
-    are recomputed one by one by the oracle."""
-    g, yb, osys, plan = systems["c1_1350bus"]
-    sc = gg.make_scenarios(g, 10000, 2001, "mc")
+_FULL = {}
+
+
+def full_set(systems, key):
+    """The whole seeded scenario set of a workload with the oracle's solution (cached: the
+    oracle solves the 10,000 1350-bus or 2,000 9000-bus flows in a few seconds on the
+    host's cores)."""
+    if key not in _FULL:
+        (g, yb, sc), = gg.workload(key)
+        osys = systems[g.name][2]
+        print(f"oracle: solving {key} ({sc.batch} flows)", flush=True)
+        _FULL[key] = (sc, osys.solve(sc.sbus, sc.v0))
+    return _FULL[key]
+
+
+@pytest.mark.parametrize("key,name", [("c1", "c1_1350bus"), ("c2", "c2_9000bus")])
+def test_full_set_fp64_matches_oracle(systems, key, name):
+    """Every instance of the 10,000-scenario 1350-bus set and of the 2,000-scenario
+    9000-bus set, in the benchmark's launch configuration, against the oracle: the FP64
+    full-solve bar (identical flags and iteration counts, |V| and angle within 1e-6)."""
+    g, yb, osys, plan = systems[name]
+    sc, ro = full_set(systems, key)
     y, s, v = to_dev(yb, sc)
+    print(f"{key}: FP64 solve of {sc.batch} flows, config {plan.resolve(sc.batch)}", flush=True)
     rg = pf.solve_batch(plan, y, s, v)
     torch.cuda.synchronize()
-    idx = np.random.default_rng(0).choice(10000, 120, replace=False)
-    ro = osys.solve(sc.sbus[idx], sc.v0[idx])
-
-    class Sub:
-        pass
-    sub = Sub()
-    sub.v = rg.v[torch.from_numpy(idx).to(DEV)]
-    sub.iters = rg.iters[torch.from_numpy(idx).to(DEV)]
-    sub.converged = rg.converged[torch.from_numpy(idx).to(DEV)]
-    sub.status = rg.status[torch.from_numpy(idx).to(DEV)]
-    compare_solve(osys, ro, sub)
+    bl = compare_solve(osys, ro, rg, sc.sbus)
+    print(f"{key}: {len(bl)} borderline instances; converged {rg.converged.float().mean().item():.5f}")
+    assert len(bl) <= sc.batch // 100
     assert rg.converged.float().mean().item() > 0.99
 
 
-def test_solve_parity_config2_sampled(systems):
-    g, yb, osys, plan = systems["c2_9000bus"]
-    sc = gg.make_scenarios(g, 2000, 2002, "mc")
+@pytest.mark.parametrize("key,name", [("c1", "c1_1350bus"), ("c2", "c2_9000bus")])
+def test_full_set_fp32lu_matches_oracle(systems, key, name):
+    """The same sets with the FP32 Jacobian, refactorization and substitutions: every
+    instance the oracle converges converges, meets the oracle's FP64 mismatch test at the
+    returned V, and lies within 1e-6 of the oracle; the extra iterations are bounded by 2
+    (observed: none or one)."""
+    g, yb, osys, plan = systems[name]
+    sc, ro = full_set(systems, key)
     y, s, v = to_dev(yb, sc)
-    rg = pf.solve_batch(plan, y, s, v)
+    print(f"{key}: FP32-LU solve of {sc.batch} flows, config {plan.resolve(sc.batch, pf.PF_FP32_LU)}", flush=True)
+    rg = pf.solve_batch(plan, y, s, v, precision=pf.PF_FP32_LU)
     torch.cuda.synchronize()
-    idx = np.random.default_rng(1).choice(2000, 24, replace=False)
-    ro = osys.solve(sc.sbus[idx], sc.v0[idx])
-
-    class Sub:
-        pass
-    sub = Sub()
-    ii = torch.from_numpy(idx).to(DEV)
-    sub.v, sub.iters, sub.converged, sub.status = rg.v[ii], rg.iters[ii], rg.converged[ii], rg.status[ii]
-    compare_solve(osys, ro, sub)
+    _, extra = compare_fp32lu(osys, ro, rg, sc.sbus, name=key)
+    assert extra.size and extra.max() <= 2 and extra.mean() <= 0.5
 
 
 # ----------------------------------------------------------------- edge cases
@@ -315,7 +295,7 @@ def test_nonfinite_instance_is_isolated(systems):
     assert st[5] == pf.PF_ST_NONFINITE and st[21] == pf.PF_ST_NONFINITE
     mask = np.ones(40, bool); mask[[5, 21]] = False
     assert rg.converged.cpu().numpy()[mask].all()
-    compare_solve(osys, ro, rg)
+    compare_solve(osys, ro, rg, sb)
 
 
 def test_batch_of_one_and_deterministic(systems):
@@ -325,7 +305,7 @@ def test_batch_of_one_and_deterministic(systems):
     r1 = pf.solve_batch(plan, y, s, v)
     r2 = pf.solve_batch(plan, y, s, v)
     assert torch.equal(r1.v, r2.v) and torch.equal(r1.iters, r2.iters)
-    compare_solve(osys, osys.solve(sc.sbus, sc.v0), r1)
+    compare_solve(osys, osys.solve(sc.sbus, sc.v0), r1, sc.sbus)
 
 
 @pytest.mark.parametrize("name,B,prec,tile,waves", [("c1_1350bus", 48, pf.PF_FP64, 8, 8),
@@ -341,13 +321,16 @@ def test_long_slot_count_does_not_change_results(systems, name, B, prec, tile, w
     y, s, v = to_dev(yb, sc)
     kw = dict(precision=prec, tile=tile, waves=waves)
     ref = pf.solve_batch(plan, y, s, v, long_slots=1, **kw)
-    for ls in (2, 3, 5, 8, 0):
+    for ls in (2, 3, 5, 8, 10, 11, 12, 0):
         print(f"{name} precision {prec} long_slots {ls}", flush=True)
         r = pf.solve_batch(plan, y, s, v, long_slots=ls, **kw)
         torch.cuda.synchronize()
         assert torch.equal(r.v, ref.v) and torch.equal(r.iters, ref.iters) and torch.equal(r.status, ref.status), ls
-    if prec == pf.PF_FP64 and name == "c1_1350bus":
-        compare_solve(osys, osys.solve(sc.sbus, sc.v0), ref)
+    ro = osys.solve(sc.sbus, sc.v0)
+    if prec == pf.PF_FP64:
+        compare_solve(osys, ro, ref, sc.sbus)
+    else:
+        compare_fp32lu(osys, ro, ref, sc.sbus, name=name)
 
 
 def test_natural_and_user_orderings_agree(systems):
@@ -358,36 +341,16 @@ def test_natural_and_user_orderings_agree(systems):
     for kw in (dict(ordering=pf.PF_ORDER_NATURAL), dict(ordering=pf.PF_ORDER_USER, user_perm=osys.order())):
         plan = pf.Plan.from_ybus(yb, g.bus_type, **kw)
         rg = pf.solve_batch(plan, y, s, v)
-        compare_solve(osys, ro, rg)
+        compare_solve(osys, ro, rg, sc.sbus)
 
 
-# ----------------------------------------------------------------- FP32-LU inexact Newton
-@pytest.mark.parametrize("name,B", [("c1_1350bus", 256), ("c2_9000bus", 64)])
-def test_fp32_lu_converges_to_fp64_answer(systems, name, B):
-    g, yb, osys, plan = systems[name]
-    sc = gg.make_scenarios(g, B, 2002, "mc")
-    ro = osys.solve(sc.sbus, sc.v0)
-    y, s, v = to_dev(yb, sc)
-    rg = pf.solve_batch(plan, y, s, v, precision=pf.PF_FP32_LU)
-    cv = rg.converged.cpu().numpy().astype(bool)
-    vg = rg.v.cpu().numpy()
-    both = cv & ro.converged
-    assert both.sum() >= 0.98 * ro.converged.sum()
-    err = np.max(np.abs(vg[both] - ro.v[both]))
-    assert err <= 1e-6, err
-    extra = rg.iters.cpu().numpy()[both] - ro.iters[both]
-    print(f"\n{name}: FP32-LU max |V|/angle error vs oracle {err:.2e}; extra iterations "
-          f"mean {extra.mean():.2f}, max {extra.max()}")
-    # the FP64 mismatch at the returned V meets the tolerance
-    F, nf = pf.eval_mismatch(plan, y, s, rg.v)
-    assert (nf.cpu().numpy()[both] < 1e-8).all()
-
-
+# ----------------------------------------------------------------- warm-start entry point
 def test_warm_entry_point_restarts_failed_instances(systems):
     """pf_solve_batch_warm: instances whose start is broken (|V| = 0 gives a non-finite
     mismatch at once, before any update) restart from the fallback inside the kernel and
-    end exactly where the plain flat-start solve ends; far-off starts stay within the
-    shared max_iter update budget; the other instances are untouched by the fallback."""
+    end exactly where the plain flat-start solve ends; a far-off start either converges
+    from there or restarts with a fresh max_iter budget, so every instance the flat-start
+    solve converges also converges; the other instances are untouched by the fallback."""
     g, yb, osys, plan = systems["c4_100bus"]
     sc = gg.make_scenarios(g, 96, 31, "mc")
     y, s, vflat = to_dev(yb, sc)
@@ -404,11 +367,11 @@ def test_warm_entry_point_restarts_failed_instances(systems):
             assert torch.equal(r.status[sl], r0.status[sl])
             assert torch.equal(r.v[sl], r0.v[sl]) and torch.equal(r.iters[sl], r0.iters[sl])
         # far-off starts: converged from there (possibly to another power-flow solution) or
-        # restarted from the flat start within the shared update budget
-        assert bool((r.iters[32:64] <= 10).all())
+        # restarted from the flat start with a fresh budget of max_iter updates
+        assert bool((r.iters[32:64] <= 20).all())
         st = r.status[32:64].cpu().numpy()
         assert np.isin(st, [pf.PF_ST_CONVERGED, pf.PF_ST_MAXITER, pf.PF_ST_NONFINITE, pf.PF_ST_PIVOT]).all()
-        assert bool(r.converged[32:64].float().mean() >= 0.5)
+        assert bool((r.converged[32:64] >= r0.converged[32:64]).all())
     # without the fallback the broken starts fail
     rn = pf.solve_batch(plan, y, s, v0)
     torch.cuda.synchronize()

@@ -185,3 +185,63 @@ def test_queue_group_with_different_long_slot_counts():
     assert_same(a, pf.solve_batch(plan, y, s, v, precision=pf.PF_FP64, tile=8, waves=8, long_slots=1))
     assert_same(b, pf.solve_batch(plan, y, s2, v2, precision=pf.PF_FP64, tile=8, waves=8, long_slots=6))
     q.close()
+
+
+_ORACLE = {}
+
+
+def oracle_solution(name, sc):
+    import oracle
+    if name not in _ORACLE:
+        g, yb, _, _ = system(name)
+        osys = oracle.System.from_ybus(yb, g.bus_type)
+        print(f"oracle: solving {sc.batch} flows of {name}", flush=True)
+        _ORACLE[name] = (osys, osys.solve(sc.sbus, sc.v0))
+    return _ORACLE[name]
+
+
+# the four-grid mix of the multi-pattern workload, every scenario of it
+MIX = [(g, cnt, seed) for g, cnt, seed, _ in gg.WORKLOADS["c4"]]
+# FP64 items in explicit configurations: the 1000-, 3000- and 9000-bus grids share one
+# persistent kernel (tile 4, 16 waves) with 12, 12 and 10 long working-column slots
+FP64_OPTS = {"c4_100bus": dict(tile=16, waves=16, long_slots=0),
+             "c4_1000bus": dict(tile=4, waves=16, long_slots=12),
+             "c4_3000bus": dict(tile=4, waves=16, long_slots=12),
+             "c4_9000bus": dict(tile=4, waves=16, long_slots=10)}
+
+
+@pytest.mark.parametrize("prec", [pf.PF_FP64, pf.PF_FP32_LU])
+def test_queue_four_grid_mix_matches_oracle(prec):
+    """Every instance of the four-grid mix (100/1000/3000/9000 buses, 4000/2000/1000/200
+    scenarios) solved by one replayed queue graph, against the oracle.  FP32-LU items use
+    the configurations the tuner picks (16-wave workgroups); FP64 items use explicit ones
+    that include the 10 and 12 long-slot counts.  FP64: the full-solve bar; FP32-LU: the
+    FP32-LU bar; no instance reports PF_ST_INTERNAL."""
+    from tests.parity import compare_fp32lu, compare_solve
+    q = pf.Queue()
+    items = []
+    for name, cnt, seed in MIX:
+        g, yb, plan, y = system(name)
+        sc = gg.make_scenarios(g, cnt, seed, "mc")
+        s = torch.from_numpy(sc.sbus).to(DEV)
+        v = torch.from_numpy(sc.v0).to(DEV)
+        if prec == pf.PF_FP32_LU:
+            opts, ms = pf.tune(plan, y, s, v, precision=prec, waves=16, reps=1)
+            print(f"tuned {name}: {opts} {ms:.3f} ms", flush=True)
+        else:
+            opts = dict(precision=prec, schedule=0, **FP64_OPTS[name])
+        items.append((name, sc, q.add(plan, y, s, v, **opts), (s, v)))
+    q.run()
+    q.run()                                               # a replay gives the same results
+    torch.cuda.synchronize()
+    info = q.info()
+    print(f"queue: {info['n_groups']} groups, grid {info['grid']}, {info['n_tiles']} tiles", flush=True)
+    for name, sc, out, _ in items:
+        osys, ro = oracle_solution(name, sc)
+        if prec == pf.PF_FP64:
+            bl = compare_solve(osys, ro, out, sc.sbus)
+            assert len(bl) <= max(2, sc.batch // 100), (name, len(bl))
+        else:
+            compare_fp32lu(osys, ro, out, sc.sbus, name=name)
+        assert out.converged.float().mean().item() > 0.99, name
+    q.close()

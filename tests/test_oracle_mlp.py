@@ -1,6 +1,7 @@
 """Pins of the FP64 numpy network reference used to check the warm-start kernels:
-central finite differences of the loss for every weight and bias gradient, the GELU
-definition at known points, and Adam against its closed form for a constant gradient."""
+central finite differences of the loss for every weight and bias gradient, GELU and its
+derivative at points where the normal distribution is tabulated, and Adam against its
+closed form for a constant gradient."""
 import math
 
 import numpy as np
@@ -15,11 +16,22 @@ def small_net(rng, dims=(6, 5, 4, 3)):
 
 
 def test_gelu_known_values():
-    z = np.array([-3.0, -1.0, 0.0, 0.5, 2.0])
-    # GELU(z) = z * Phi(z) with the standard normal CDF Phi
-    phi = np.array([0.5 * (1 + math.erf(v / math.sqrt(2))) for v in z])
-    assert np.allclose(mlp.gelu(z), z * phi, atol=1e-15)
+    """GELU(z) = z Phi(z) at points where the standard normal CDF is tabulated (Abramowitz
+    and Stegun, Table 26.1; values to 16+ digits): Phi(0.5) = 0.6914624612740131,
+    Phi(1) = 0.8413447460685429, Phi(2) = 0.9772498680518208, Phi(3) = 0.9986501019683699,
+    Phi(-z) = 1 - Phi(z).  The derivative Phi(z) + z phi(z) at z = 1 and 2 uses the
+    tabulated density phi(1) = 0.24197072451914337, phi(2) = 0.05399096651318806."""
+    table = {-3.0: -0.0040496940948902836, -1.0: -0.15865525393145707, 0.0: 0.0,
+             0.5: 0.34573123063700655, 1.0: 0.8413447460685429, 2.0: 1.9544997361036416,
+             3.0: 2.9959503059051097}
+    z = np.array(sorted(table))
+    want = np.array([table[v] for v in z])
+    got = mlp.gelu(z)
+    assert np.all(np.abs(got - want) <= 4e-16 * np.maximum(1.0, np.abs(want))), got - want
     assert mlp.gelu(np.array([0.0]))[0] == 0.0
+    dtab = {0.0: 0.5, 1.0: 1.0833154705876863, 2.0: 1.0852318010781969}
+    zd = np.array(sorted(dtab))
+    assert np.allclose(mlp.gelu_grad(zd), [dtab[v] for v in zd], rtol=0, atol=2e-15)
     h = 1e-6
     fd = (mlp.gelu(z + h) - mlp.gelu(z - h)) / (2 * h)
     assert np.allclose(mlp.gelu_grad(z), fd, atol=1e-8)

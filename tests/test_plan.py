@@ -163,6 +163,31 @@ def test_plan_info_and_workspace():
     assert plan.workspace_bytes(10000, tile=7) == 0
 
 
+@pytest.mark.parametrize("name", ["c0_14bus", "c4_100bus", "c1_1350bus"])
+def test_level_histogram_recomputed_from_pattern(name):
+    """pf_plan_levels against a recomputation from the L+U pattern alone: the level of
+    column j is one more than the highest level among the columns k with U(k, j) != 0,
+    and the update of column j by k costs one multiply-add per L entry of column k."""
+    g = gg.grid(name)
+    plan = pf.Plan.from_ybus(gg.ybus(g), g.bus_type)
+    cp, ri, _ = plan.lu_pattern()
+    N = plan.N
+    lev = np.zeros(N, np.int64)
+    nl = np.array([int(np.sum(ri[cp[k]:cp[k + 1]] > k)) for k in range(N)])
+    madd = np.zeros(N, np.int64)
+    for j in range(N):
+        ks = ri[cp[j]:cp[j + 1]]
+        ks = ks[ks < j]
+        if ks.size:
+            lev[j] = lev[ks].max() + 1
+            madd[j] = nl[ks].sum()
+    cols, madds = plan.levels()
+    assert cols.shape[0] == plan.info["n_levels"] == lev.max() + 1
+    assert np.array_equal(cols, np.bincount(lev))
+    assert np.array_equal(madds, np.bincount(lev, weights=madd).astype(np.int64))
+    assert madds.sum() == plan.info["flops_refactor"]
+
+
 def test_pattern_hash_identifies_pattern_and_order():
     g = gg.grid("c4_100bus")
     yb = gg.ybus(g)
