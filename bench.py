@@ -63,28 +63,68 @@ def algorithmic_bytes(info, iters: np.ndarray, precision_fp32: bool) -> float:
     return float(iters.astype(np.int64).sum()) * per_iter + iters.shape[0] * (32 * n + 8 * N + 48 * n)
 
 
-def cpu_baseline(g, yb, sc, tol, max_iter, target_s=12.0):
-    """The FP64 oracle on the host cores: a probe sizes a sample of the scenarios (the whole
-    set, repeated, when one pass is short) to about target_s seconds of CPU work."""
-    import oracle
-    osys = oracle.System.from_ybus(yb, g.bus_type)
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    probe = min(64, sc.batch)
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _sized_rate(solve, sbus, v0, target_s):
+    """Converged flows per second of solve(sbus, v0) on a sample of the scenarios sized by a
+    64-scenario probe to about target_s seconds (the whole set, repeated, when one pass is
+    shorter).  Returns (rate, scenarios, passes, seconds)."""
+    B = sbus.shape[0]
+    probe = min(64, B)
     t0 = time.perf_counter()
-    osys.solve(sc.sbus[:probe], sc.v0[:probe], tol=tol, max_iter=max_iter, threads=cores)
+    solve(sbus[:probe], v0[:probe])
     dt = max(time.perf_counter() - t0, 1e-4)
     want = int(max(probe, probe * target_s / dt))
-    count = min(sc.batch, want)
+    count = min(B, want)
     reps = max(1, min(1000, want // max(count, 1)))
     t0 = time.perf_counter()
     n_conv = 0
     for _ in range(reps):
-        r = osys.solve(sc.sbus[:count], sc.v0[:count], tol=tol, max_iter=max_iter, threads=cores)
-        n_conv += int(r.converged.sum())
+        n_conv += int(np.asarray(solve(sbus[:count], v0[:count])).sum())
     dt = time.perf_counter() - t0
-    return {"value": float(n_conv / dt), "unit": "flows/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"first {count} of the {sc.batch} scenarios x {reps} passes, FP64 oracle (own "
-                      f"minimum-degree order, pivoting left-looking LU), {cores} threads, {dt:.1f} s"}
+    return n_conv / dt, count, reps, dt
+
+
+def cpu_baseline(g, yb, sc, tol, max_iter, plan=None, target_s=8.0):
+    """The FP64 oracle on the host cores (every core, then one), plus the batched CPU engine
+    of the library (pf_cpu_solve_batch: mini-batches of 8 instances in SIMD lanes) on every
+    core and on one, each on a sample of the scenarios sized to about target_s seconds."""
+    import oracle
+    osys = oracle.System.from_ybus(yb, g.bus_type)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    ora = lambda th: (lambda s, v: osys.solve(s, v, tol=tol, max_iter=max_iter, threads=th).converged)
+    rate, count, reps, dt = _sized_rate(ora(cores), sc.sbus, sc.v0, target_s)
+    rate1, count1, reps1, dt1 = _sized_rate(ora(1), sc.sbus, sc.v0, target_s / 2)
+    out = {"value": float(rate), "unit": "flows/s", "cores": int(cores), "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": f"first {count} of the {sc.batch} scenarios x {reps} passes, FP64 oracle (own "
+                     f"minimum-degree order, pivoting left-looking LU), {cores} threads, {dt:.1f} s",
+           "one_core": {"value": round(rate1, 1), "unit": "flows/s", "cores": 1,
+                        "sample": f"first {count1} scenarios x {reps1} passes, {dt1:.1f} s"}}
+    if plan is not None:
+        import paper_2101_02270_amd as pf
+        yv = yb.val
+        eng = lambda th: (lambda s, v: pf.cpu_solve_batch(plan, yv, s, v, tol=tol, max_iter=max_iter,
+                                                          threads=th).converged)
+        er, ec, erp, edt = _sized_rate(eng(cores), sc.sbus, sc.v0, target_s / 2)
+        er1, ec1, erp1, edt1 = _sized_rate(eng(1), sc.sbus, sc.v0, target_s / 4)
+        out["batched_cpu_engine"] = {
+            "value": round(er, 1), "unit": "flows/s", "cores": int(cores),
+            "kind": "pf_cpu_solve_batch (left-looking refactorization over mini-batches of 8 in SIMD "
+                    "lanes, worker threads)",
+            "sample": f"first {ec} scenarios x {erp} passes, {edt:.1f} s",
+            "one_core": {"value": round(er1, 1), "cores": 1, "sample": f"first {ec1} scenarios x {erp1} passes, "
+                                                                        f"{edt1:.1f} s"}}
+    return out
 
 
 def timed_solves(fn, steps, warmup):
@@ -97,6 +137,104 @@ def timed_solves(fn, steps, warmup):
         out = fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps, out
+
+
+def status_histogram(status) -> dict:
+    names = {0: "converged", 1: "maxiter", 2: "nonfinite", 3: "pivot", -1: "internal"}
+    st = np.asarray(status).astype(np.int64)
+    return {names.get(int(k), str(int(k))): int((st == k).sum()) for k in np.unique(st)}
+
+
+def event_ms(fn, reps, stream):
+    """Median duration in ms of fn() between two events on stream (one untimed call first)."""
+    import torch
+    fn()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def lu_fraction(plan, y, s, v, precision_fp32: bool, reps: int = 5) -> dict:
+    """Roofline position of the Jacobian store, refactorization and substitutions alone:
+    one Newton step at V (pf_eval_step: mismatch pass with Jacobian stores, refactorization
+    with forward substitution, back substitution) minus the plain mismatch pass at the same
+    V (pf_eval_mismatch: no Jacobian stores), both writing one [B][N] vector.  Algorithmic
+    bytes per instance: refactorization 2 b nnz_lu + substitutions b nnz_lu + 16 N, and the
+    Jacobian store b nnz_lu (b = bytes per LU value)."""
+    import torch
+    import paper_2101_02270_amd as pf
+    prec = pf.PF_FP32_LU if precision_fp32 else pf.PF_FP64
+    B = int(v.shape[0])
+    info = plan.info
+    b = 4 if precision_fp32 else 8
+    ws = torch.empty(plan.workspace_bytes(B, prec) + 256, dtype=torch.uint8, device=v.device)
+    st = torch.cuda.current_stream()
+    t_m = event_ms(lambda: pf.eval_mismatch(plan, y, s, v, precision=prec, workspace=ws), reps, st)
+    t_s = event_ms(lambda: pf.eval_step(plan, y, s, v, precision=prec, workspace=ws), reps, st)
+    lu_b = float(B) * (3 * b * info["nnz_lu"] + 16 * info["n_unknowns"])
+    jac_b = float(B) * b * info["nnz_lu"]
+    dt = max(t_s - t_m, 1e-6) * 1e-3
+    return {"mismatch_ms": round(t_m, 4), "step_ms": round(t_s, 4), "lu_ms": round(t_s - t_m, 4),
+            "lu_bytes": lu_b, "jacobian_store_bytes": jac_b,
+            "frac_lu": round(lu_b / dt / 1e9 / HBM_PEAK_GBS, 4),
+            "frac_lu_with_jacobian_store": round((lu_b + jac_b) / dt / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def grid9000_variant(steps, warmup, log):
+    """The 9000-bus grid with 2,000 Monte Carlo scenarios in FP64 and FP32-LU on the same
+    scenarios: flows/s, convergence, status counts, the |V| / angle error of every
+    converged instance against the FP64 oracle and the FP32-LU extra iterations, plus the
+    refactorization-only roofline position of both."""
+    import torch
+    import gridgen as gg
+    import oracle
+    import paper_2101_02270_amd as pf
+    dev = torch.device("cuda", 0)
+    (g, yb, sc), = gg.workload("c2")
+    plan = pf.Plan.from_ybus(yb, g.bus_type)
+    y = torch.from_numpy(yb.val).to(dev)
+    s = torch.from_numpy(np.ascontiguousarray(sc.sbus)).to(dev)
+    v = torch.from_numpy(np.ascontiguousarray(sc.v0)).to(dev)
+    t0 = time.perf_counter()
+    ro = oracle.System.from_ybus(yb, g.bus_type).solve(sc.sbus, sc.v0, threads=len(os.sched_getaffinity(0)))
+    log(f"[bench] 9000-bus oracle reference solved in {time.perf_counter() - t0:.1f} s")
+    out = {"workload": WORKLOADS["c2"]["desc"], "stress_factor": g.scale, "batch": sc.batch}
+    its = {}
+    for prec, name in ((pf.PF_FP64, "fp64"), (pf.PF_FP32_LU, "fp32lu")):
+        ws = torch.empty(plan.workspace_bytes(sc.batch, prec) + 256, dtype=torch.uint8, device=dev)
+        dt, r = timed_solves(lambda: pf.solve_batch(plan, y, s, v, precision=prec, workspace=ws), steps, warmup)
+        cv = r.converged.cpu().numpy().astype(bool)
+        it = r.iters.cpu().numpy()
+        vv = r.v.cpu().numpy()
+        both = cv & ro.converged
+        its[name] = (it, both)
+        info = plan.info
+        abytes = float(it.astype(np.int64).sum()) * info["bytes_iter_fp32" if prec else "bytes_iter_fp64"] + \
+            sc.batch * (32 * g.n + 8 * info["n_unknowns"] + 48 * g.n)
+        out[name] = {"flows_per_s": round(int(cv.sum()) / dt, 1), "ms": round(dt * 1e3, 3),
+                     "converged_fraction": round(float(cv.mean()), 5),
+                     "oracle_converged_fraction": round(float(ro.converged.mean()), 5),
+                     "status": status_histogram(r.status.cpu().numpy()),
+                     "iterations_mean": round(float(it[cv].mean()), 4),
+                     "max_abs_vm_error_vs_oracle": float(np.abs(vv[both, :, 0] - ro.v[both, :, 0]).max()),
+                     "max_abs_angle_error_vs_oracle": float(np.abs(vv[both, :, 1] - ro.v[both, :, 1]).max()),
+                     "iterations_equal_oracle_fraction": round(float((it[both] == ro.iters[both]).mean()), 5),
+                     "roofline_frac": round(abytes / dt / 1e9 / HBM_PEAK_GBS, 4),
+                     "lu_only": lu_fraction(plan, y, s, v, bool(prec))}
+    (i64, b64), (i32, b32) = its["fp64"], its["fp32lu"]
+    both = b64 & b32
+    extra = i32[both] - i64[both]
+    out["fp32lu"]["extra_iterations_vs_fp64"] = {"mean": round(float(extra.mean()), 4), "max": int(extra.max()),
+                                                 "histogram_from_min": np.bincount(extra - extra.min()).tolist(),
+                                                 "min": int(extra.min())}
+    return out
 
 
 def warm_start_variants(steps, warmup, epochs, log):
@@ -159,8 +297,13 @@ def warm_start_variants(steps, warmup, epochs, log):
         both = cw & ref.converged.cpu().numpy().astype(bool)
         dv = float(np.abs(rw.v.cpu().numpy()[both] - ref.v.cpu().numpy()[both]).max()) if both.any() else None
         out[pname + "_flat"] = {"flows_per_s": round(int(cf.sum()) / dt_f, 1), "ms": round(dt_f * 1e3, 3),
+                                "converged_fraction": round(float(cf.mean()), 5),
+                                "status": status_histogram(rf.status.cpu().numpy()),
                                 "iterations_mean": round(float(rf.iters.cpu().numpy()[cf].mean()), 4)}
         out[pname + "_warm"] = {"flows_per_s": round(int(cw.sum()) / dt_w, 1), "ms": round(dt_w * 1e3, 3),
+                                "converged_fraction": round(float(cw.mean()), 5),
+                                "status": status_histogram(rw.status.cpu().numpy()),
+                                "lost_vs_flat": int((cf & ~cw).sum()),
                                 "iterations_mean": round(float(rw.iters.cpu().numpy()[cw].mean()), 4),
                                 "fallbacks": n_fb, "max_dv_vs_fp64_flat": dv}
     return out
@@ -212,6 +355,8 @@ def queue_variant(steps, warmup, log, precision_name="fp32lu"):
         both = o.converged.bool() & rs.converged.bool()
         dv = float((o.v - rs.v)[both].abs().max().item()) if bool(both.any()) else None
         per_grid[g.name] = {"scenarios": int(v.shape[0]), "config": best,
+                            "converged_fraction": round(float(conv.mean()), 5),
+                            "status": status_histogram(o.status.cpu().numpy()),
                             "iterations_mean": round(float(o.iters.cpu().numpy()[conv].mean()), 4),
                             "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
                             "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
@@ -286,6 +431,8 @@ def main():
     ap.add_argument("--count", type=int, default=0, help="cap the scenario count (testing only)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32-LU and learned-warm-start variants")
+    ap.add_argument("--no-lu-only", action="store_true",
+                    help="skip the single-step timing of the refactorization and substitutions")
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scales the HBM "
@@ -299,13 +446,22 @@ def main():
 
     import torch
     if args.copy_calibration:
+        # (1) a plain 256 MiB copy; (2) a copy that reads 64-byte segments (8 of every 16
+        # doubles, the size of one FP64 tile entry of 8 instances) into a contiguous
+        # 128 MiB buffer: the HBM byte counters of these launches scale the solver's
         n = 256 * 1024 * 1024 // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
+        c = torch.empty((n // 16, 8), dtype=torch.float64, device="cuda")
+        a2 = a.view(n // 16, 16)
         for _ in range(3):
             b.copy_(a)
+        for _ in range(3):
+            c.copy_(a2[:, :8])
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_per_direction": n * 8, "launches": 3}))
+        print(json.dumps({"copy_bytes_per_direction": n * 8, "launches": 3,
+                          "segment_copy_bytes_read": n * 4, "segment_copy_bytes_written": n * 4,
+                          "segment_bytes": 64}))
         return
     import gridgen as gg
     import paper_2101_02270_amd as pf
@@ -318,12 +474,17 @@ def main():
     print(f"[bench] workload {args.workload}: n={g.n} batch={sc.batch} precision={args.precision}",
           file=sys.stderr, flush=True)
 
+    dev = torch.device("cuda", 0)
+    # the HIP runtime is initialised before the analysis is timed, so analyze_ms is the
+    # pattern analysis plus the plan upload only (the paper's one-time "init")
+    torch.zeros(1, device=dev)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan = pf.Plan.from_ybus(yb, g.bus_type)
+    torch.cuda.synchronize()
     analyze_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info
 
-    dev = torch.device("cuda", 0)
     y = torch.from_numpy(yb.val).to(dev)
     s = torch.from_numpy(np.ascontiguousarray(sc.sbus)).to(dev)
     v0 = torch.from_numpy(np.ascontiguousarray(sc.v0)).to(dev)
@@ -379,8 +540,9 @@ def main():
         "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "batch": B, "n_bus": g.n, "precision": args.precision,
-                   "start": "flat", "tol": tol, "max_iter": max_iter},
+                   "start": "flat", "tol": tol, "max_iter": max_iter, "stress_factor": g.scale},
         "converged_fraction": round(n_conv / B, 5),
+        "status": status_histogram(out.status.cpu().numpy()),
         "iterations_mean": round(float(iters[conv].mean()) if n_conv else 0.0, 4),
         "analyze_ms": round(analyze_ms, 2),
         "plan": {k: info[k] for k in ("n_unknowns", "nnz_lu", "n_levels", "flops_refactor", "max_col")},
@@ -391,8 +553,13 @@ def main():
                      "kernel": "nr_tile_kernel", "kernel_ms": round(kernel_ms, 4),
                      "algorithmic_bytes_per_launch": abytes},
     }
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    if not args.no_lu_only:
+        res["lu_only"] = lu_fraction(plan, y, s, v0, fp32)
+        log(f"[bench] refactorization + substitutions alone: {res['lu_only']}")
     if not args.no_variants and args.workload == "c1" and not args.count:
-        log = lambda m: print(m, file=sys.stderr, flush=True)
+        log("[bench] variants: 9000-bus grid, FP64 and FP32-LU against the oracle")
+        res["variants_9000bus"] = grid9000_variant(max(2, args.steps // 2), 1, log)
         log("[bench] variants: FP32-LU and learned warm start on the held-out set")
         res["variants"] = warm_start_variants(max(2, args.steps // 2), 1, args.epochs, log)
         log("[bench] variants: four-grid queue with tuned configurations")
@@ -403,7 +570,7 @@ def main():
         res["variants"]["host_resident"] = host_resident_variant(max(2, args.steps // 2), 1)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(g, yb, sc, tol, max_iter)
+        res["cpu_baseline"] = cpu_baseline(g, yb, sc, tol, max_iter, plan=plan)
     print(json.dumps(res), flush=True)
 
 

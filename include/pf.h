@@ -359,6 +359,41 @@ int pf_cpu_solve_batch(pf_plan plan, int32_t batch, const double *ybus, const do
                        double tol, int32_t max_iter, int32_t threads, double *v_out, int32_t *iters_out,
                        uint8_t *converged_out, int8_t *status_out);
 
+/*
+ * Second chance for instances whose refactorization failed (Sec. 3.2: a task that does not
+ * converge because of numerical trouble in the LU refactorization is solved again with a
+ * pivoting numerical factorization; Sec. 4.1: partial pivoting updates the row permutation
+ * of Eq. 3 to avoid tiny pivots).  The GPU refactorization keeps the symmetric pre-order
+ * and diagonal pivots and reports such an instance as PF_ST_PIVOT (a pivot that is not
+ * finite, not above 1e-300 in magnitude, or below 1e-14 (FP64) / 1e-7 (FP32-LU) times the
+ * largest magnitude in its column of A = P J P^T) or, when a bad step made the mismatch
+ * non-finite, PF_ST_NONFINITE.
+ *
+ * pf_cpu_solve_pivoting: Newton-Raphson in FP64 on the host with a fresh left-looking
+ * Gilbert-Peierls LU with threshold partial pivoting every iteration (the diagonal row is
+ * kept while its magnitude is at least 0.1 times the column's largest candidate; fill
+ * follows the pivots), same stopping rules and outputs as pf_solve_batch.
+ *   ybus [host]  nnz_y complex values, or batch x nnz_y when ybus_batched
+ *   sbus, v0, v_out, iters_out, converged_out, status_out (may be NULL) [host] as
+ *                pf_solve_batch; threads = 0 uses every online core.
+ * Synchronous; needs no device.  PF_EINVAL for invalid arguments, PF_ENOMEM.
+ *
+ * pf_solve_fallback: after a pf_solve_batch(_warm) call with the same arguments (device
+ * pointers, same stream), waits for the stream, reads status_out and re-solves every
+ * instance reporting PF_ST_PIVOT or PF_ST_NONFINITE from its v0 as pf_cpu_solve_pivoting
+ * does, on the host (only those instances' inputs are copied), then writes its V,
+ * iteration count, flag and status back over the GPU result.  status_out is required.
+ * *n_resolved (may be NULL) receives the number of instances re-solved.  Synchronous with
+ * respect to the host; PF_EDEVICE when a copy or the synchronisation fails.
+ */
+int pf_cpu_solve_pivoting(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus_batched,
+                          const double *sbus, const double *v0, double tol, int32_t max_iter, int32_t threads,
+                          double *v_out, int32_t *iters_out, uint8_t *converged_out, int8_t *status_out);
+int pf_solve_fallback(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus_batched, const double *sbus,
+                      const double *v0, double tol, int32_t max_iter, int32_t threads, double *v_out,
+                      int32_t *iters_out, uint8_t *converged_out, int8_t *status_out, int32_t *n_resolved,
+                      void *stream);
+
 /* Release the plan and its device memory. */
 void pf_plan_destroy(pf_plan plan);
 

@@ -29,7 +29,7 @@ EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
             "pf_mlp_features", "pf_mlp_warm_v0", "pf_queue_create", "pf_queue_add",
             "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune", "pf_solve_batch_warm",
             "pf_resolve_opts", "pf_branch_flows", "pf_plan_schedule", "pf_solve_host",
-            "pf_plan_levels", "pf_cpu_solve_batch"]
+            "pf_plan_levels", "pf_cpu_solve_batch", "pf_cpu_solve_pivoting", "pf_solve_fallback"]
 
 
 class PfError(RuntimeError):
@@ -80,6 +80,10 @@ def lib():
         L.pf_plan_levels.argtypes = [_vp, _i32p, ctypes.POINTER(ctypes.c_int64)]
         L.pf_cpu_solve_batch.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                          ctypes.c_int32, _vp, _vp, _vp, _vp]
+        L.pf_cpu_solve_pivoting.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_double,
+                                            ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp]
+        L.pf_solve_fallback.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_double,
+                                        ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _i32p, _vp]
         L.pf_plan_lu_pattern.argtypes = [_vp, _i32p, _i32p, _i32p]
         L.pf_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_Opts)]
         L.pf_workspace_bytes.restype = ctypes.c_size_t
@@ -284,11 +288,14 @@ def _as_pairs(x, name):
 def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
                 precision: int = PF_FP64, tile: int = 0, waves: int = 0, workspace=None,
                 stream=None, out: Optional[Result] = None, schedule: int = 0,
-                v_fallback=None, long_slots: int = 0) -> Result:
+                v_fallback=None, long_slots: int = 0, pivot_fallback: bool = False) -> Result:
     """Run pf_solve_batch on device tensors: ybus complex128 [nnz_y] (or [B][nnz_y]: one set of
     values per instance), sbus complex128 [B][n],
     v0 float64 [B][n][2].  With v_fallback (same shape as v0) pf_solve_batch_warm runs
     instead: instances that fail from v0 restart once from v_fallback inside the kernel.
+    With pivot_fallback, pf_solve_fallback then re-solves every instance that reported
+    PF_ST_PIVOT or PF_ST_NONFINITE with a threshold-pivoting factorization (synchronises the
+    stream; out.n_resolved counts them).
     Returns device tensors (valid once the stream synchronises)."""
     torch = _torch()
     B = int(v0.shape[0])
@@ -315,6 +322,14 @@ def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 1
                                        ctypes.byref(opts), wp, avail, *outs)
         _check(rc, "pf_solve_batch_warm")
     out._workspace = workspace
+    if pivot_fallback:
+        nr = ctypes.c_int32(0)
+        rc = lib().pf_solve_fallback(plan._h, B, yp, yb_batched, sp, vp, float(tol), int(max_iter), 0,
+                                     _vp(out.v.data_ptr()), _vp(out.iters.data_ptr()),
+                                     _vp(out.converged.data_ptr()), _vp(out.status.data_ptr()),
+                                     ctypes.byref(nr), _stream_ptr(stream))
+        _check(rc, "pf_solve_fallback")
+        out.n_resolved = int(nr.value)
     return out
 
 
@@ -491,6 +506,30 @@ class HostResult:
     iters: np.ndarray      # int32 [B]
     converged: np.ndarray  # bool [B]
     status: np.ndarray     # int8 [B]
+
+
+def cpu_solve_pivoting(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
+                       threads: int = 0) -> HostResult:
+    """pf_cpu_solve_pivoting on host arrays: ybus complex128 [nnz_y] or [B][nnz_y], sbus
+    complex128 [B][n], v0 float64 [B][n][2].  Newton-Raphson with a fresh threshold-pivoting
+    sparse LU every iteration (the factorization pf_solve_fallback gives flagged instances)."""
+    y = np.ascontiguousarray(np.asarray(ybus, dtype=np.complex128)).view(np.float64)
+    s = np.ascontiguousarray(np.asarray(sbus, dtype=np.complex128)).view(np.float64)
+    v = np.ascontiguousarray(v0, dtype=np.float64)
+    B = int(v.shape[0])
+    batched = 1 if y.ndim == 2 else 0
+    if y.shape[-1] != 2 * plan.nnz_y or (batched and y.shape[0] != B) or s.shape != (B, 2 * plan.n) \
+            or v.shape != (B, plan.n, 2):
+        raise PfError("ybus, sbus or v0 has the wrong shape for this plan")
+    out = HostResult(v=np.empty((B, plan.n, 2)), iters=np.empty(B, np.int32),
+                     converged=np.empty(B, np.uint8), status=np.empty(B, np.int8))
+    rc = lib().pf_cpu_solve_pivoting(plan._h, B, _vp(y.ctypes.data), batched, _vp(s.ctypes.data),
+                                     _vp(v.ctypes.data), float(tol), int(max_iter), int(threads),
+                                     _vp(out.v.ctypes.data), _vp(out.iters.ctypes.data),
+                                     _vp(out.converged.ctypes.data), _vp(out.status.ctypes.data))
+    _check(rc, "pf_cpu_solve_pivoting")
+    out.converged = out.converged.astype(bool)
+    return out
 
 
 def cpu_solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpf_hip.so")
-SOURCES = ["pf_solver.hip", "pf_plan.cpp", "pf_mlp.hip", "pf_flows.hip", "pf_host.cpp"]
+SOURCES = ["pf_solver.hip", "pf_plan.cpp", "pf_mlp.hip", "pf_flows.hip", "pf_host.cpp", "pf_fallback.cpp"]
 # host-only sources compiled by the system C++ compiler (vectorised CPU engine) and linked in
 CPU_SOURCES = ["pf_cpu.cpp"]
 CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fno-math-errno", "-pthread"]

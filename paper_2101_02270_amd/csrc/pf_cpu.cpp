@@ -222,6 +222,12 @@ void solve_minibatch(const Job &jb, Scratch &sc, int b0)
         for (int j = 0; j < N; j++) {
             double *col = lu + (size_t)h.col_ptr[j] * W;
             double *yj = y + (size_t)j * W;
+            const int cnt = h.col_ptr[j + 1] - h.col_ptr[j];
+            // largest magnitude of the column of A, for the relative pivot test
+            double cmax[W];
+            for (int b = 0; b < W; b++) cmax[b] = 0.0;
+            for (int e = 0; e < cnt; e++)
+                for (int b = 0; b < W; b++) cmax[b] = std::fmax(cmax[b], std::fabs(col[(size_t)e * W + b]));
             for (int u = h.upd_ptr[j]; u < h.upd_ptr[j + 1]; u++) {
                 const Update &up = h.upd[u];
                 const int krel = up.krel_lcnt & 0xffff, lcnt = up.krel_lcnt >> 16;
@@ -240,10 +246,11 @@ void solve_minibatch(const Job &jb, Scratch &sc, int b0)
                 }
             }
             const int dr = h.col_diag[j];
-            const int cnt = h.col_ptr[j + 1] - h.col_ptr[j];
             const double *d = col + (size_t)dr * W;
+            // a pivot that is not finite, not above 1e-300 or below 1e-14 of its column's
+            // largest magnitude fails the instance (as on the GPU)
             for (int b = 0; b < W; b++)
-                if (!(std::fabs(d[b]) > 1e-300 && std::isfinite(d[b]))) piv[b] = 1;
+                if (!(std::fabs(d[b]) > 1e-300 && std::isfinite(d[b]) && std::fabs(d[b]) >= 1e-14 * cmax[b])) piv[b] = 1;
             for (int e = dr + 1; e < cnt; e++)
                 for (int b = 0; b < W; b++) col[(size_t)e * W + b] /= d[b];
         }

@@ -219,8 +219,12 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     R *const long_base = short_base + (size_t)NW * 2 * P.slot_rows * T;
     R *ysl = long_base + (size_t)a.n_long * 2 * P.max_col * T + (size_t)wave * 2 * T;
     R *ysl1 = ysl + T;
+    // per wavefront the largest magnitudes of its current panel's columns of A (relative
+    // pivot test)
+    R *cmx = long_base + (size_t)a.n_long * 2 * P.max_col * T + (size_t)NW * 2 * T + (size_t)wave * 2 * T;
+    R *cmx1 = cmx + T;
     unsigned char *done = reinterpret_cast<unsigned char *>(
-        long_base + (size_t)a.n_long * 2 * P.max_col * T + (size_t)NW * 2 * T);
+        long_base + (size_t)a.n_long * 2 * P.max_col * T + (size_t)NW * 4 * T);
     int *err = &s_err;
     int nprog = 0;                      // this wavefront's publications so far
 
@@ -475,12 +479,16 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             // as zero; both columns of a pair share the row list and the fill pattern) and
             // right-hand sides
             {
+                R cm0 = 0, cm1 = 0;
 #pragma unroll
                 for (int r = 0; r < A_ROWS; r++) {
                     const int e = s + r * SL;
                     if (e < cnt) {
-                        xw[e * T + t] = pf[r] ? pa0[r] : (R)0;
-                        if (two) xw1[e * T + t] = pf[r] ? pa1[r] : (R)0;
+                        const R a0 = pf[r] ? pa0[r] : (R)0, a1 = pf[r] ? pa1[r] : (R)0;
+                        xw[e * T + t] = a0;
+                        if (two) xw1[e * T + t] = a1;
+                        cm0 = fmax(cm0, fabs(a0));
+                        cm1 = fmax(cm1, fabs(a1));
                     }
                 }
                 if (s == 0) {
@@ -491,8 +499,21 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                     const bool fe = P.isj[cs + e];
                     const R v0 = LU[(size_t)(cs + e) * T + t];
                     const R v1 = two ? LU[(size_t)(cs + cnt + e) * T + t] : (R)0;
-                    xw[e * T + t] = fe ? v0 : (R)0;
-                    if (two) xw1[e * T + t] = fe ? v1 : (R)0;
+                    const R a0 = fe ? v0 : (R)0, a1 = fe ? v1 : (R)0;
+                    xw[e * T + t] = a0;
+                    if (two) xw1[e * T + t] = a1;
+                    cm0 = fmax(cm0, fabs(a0));
+                    cm1 = fmax(cm1, fabs(a1));
+                }
+                // the column maxima over the instance's sub-lanes, kept in LDS until the pivots
+#pragma unroll
+                for (int off = T; off < 64; off <<= 1) {
+                    cm0 = fmax(cm0, __shfl_xor(cm0, off));
+                    cm1 = fmax(cm1, __shfl_xor(cm1, off));
+                }
+                if (s == 0) {
+                    cmx[t] = cm0;
+                    cmx1[t] = cm1;
                 }
             }
             if (more) prefetch(pdn);
@@ -589,8 +610,12 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 ub += gcnt;
             }
             wave_sync();
+            // a pivot that is not finite, not above 1e-300, or tiny against its column of A
+            // (1e-14 of the largest magnitude in FP64, 1e-7 in FP32) fails the instance
+            constexpr R kRelPivot = sizeof(R) == 8 ? (R)1e-14 : (R)1e-7;
             const R d = xw[dr * T + t];
-            if (s == 0 && valid && !(fabs((double)d) > 1e-300 && isfinite((double)d))) s_piv[t] = 1;
+            if (s == 0 && valid && !(fabs((double)d) > 1e-300 && isfinite((double)d) && fabs(d) >= kRelPivot * cmx[t]))
+                s_piv[t] = 1;
             for (int e = dr + 1 + s; e < cnt; e += SL) xw[e * T + t] = xw[e * T + t] / d;
             wave_sync();
             if (two) {
@@ -600,7 +625,9 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 wave_sync();
                 if (s == 0) ysl1[t] = fma(-xw[(dr + 1) * T + t], ysl[t], ysl1[t]);
                 const R d1 = xw1[(dr + 1) * T + t];
-                if (s == 0 && valid && !(fabs((double)d1) > 1e-300 && isfinite((double)d1))) s_piv[t] = 1;
+                if (s == 0 && valid &&
+                    !(fabs((double)d1) > 1e-300 && isfinite((double)d1) && fabs(d1) >= kRelPivot * cmx1[t]))
+                    s_piv[t] = 1;
                 for (int e = dr + 2 + s; e < cnt; e += SL) xw1[e * T + t] = xw1[e * T + t] / d1;
                 wave_sync();
             }
@@ -876,7 +903,7 @@ static TileLayout tile_layout(const HostPlan &h, const Config &c)
 static size_t lds_bytes(const HostPlan &h, const Config &c)
 {
     const size_t rs = c.precision == PF_FP32_LU ? 4 : 8;
-    return ((size_t)c.waves * 2 * ((size_t)h.slot_rows * c.tile + c.tile) + (size_t)c.n_long * 2 * h.max_col * c.tile) * rs +
+    return ((size_t)c.waves * 2 * ((size_t)h.slot_rows * c.tile + 2 * c.tile) + (size_t)c.n_long * 2 * h.max_col * c.tile) * rs +
            (size_t)h.N;
 }
 

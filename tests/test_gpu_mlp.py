@@ -144,9 +144,11 @@ def test_warm_start_matches_oracle_on_held_out_1350bus():
     and in FP32-LU.  Every instance the oracle converges from flat start converges here
     (the restart from flat start has its own max_iter budget), every converged result
     meets the tolerance in the oracle's FP64 mismatch and equals the oracle's solution
-    within 1e-6, and the mean iteration count is below flat start's."""
+    within 1e-6, and the mean iteration count is below flat start's.  The network is the
+    bench's (3 x 512, GELU) trained on 20,000 scenarios for 30 epochs: a network trained
+    for a second or two predicts worse than the flat start."""
     import oracle
-    (g, yb, tr), = gg.workload("c3_train", count=8000)
+    (g, yb, tr), = gg.workload("c3_train", count=20000)
     (_, _, ev), = gg.workload("c3_eval", count=2000)
     plan = pf.Plan.from_ybus(yb, g.bus_type)
     y = torch.from_numpy(yb.val).to(DEV)
@@ -154,7 +156,7 @@ def test_warm_start_matches_oracle_on_held_out_1350bus():
     v_tr = torch.from_numpy(tr.v0).to(DEV)
     sol = pf.solve_batch(plan, y, s_tr, v_tr)
     ok = sol.converged.cpu().numpy().astype(bool)
-    net = ws.WarmStartNet(g.bus_type, hidden=(256, 256, 256), seed=0)
+    net = ws.WarmStartNet(g.bus_type, hidden=(512, 512, 512), seed=0)
     mu_x, sd_x = ws.feature_stats(net, tr.sbus[ok], tr.v0[ok])
     Y = ws.targets_from_solution(net, sol.v.cpu().numpy()[ok])
     mu_y, sd_y = ws.target_stats(Y)
@@ -162,7 +164,7 @@ def test_warm_start_matches_oracle_on_held_out_1350bus():
     idx = torch.from_numpy(np.flatnonzero(ok)).to(DEV)
     X = net.features(s_tr.index_select(0, idx).contiguous(), v_tr.index_select(0, idx).contiguous())
     Yn = torch.from_numpy(((Y - mu_y) / sd_y).astype(np.float32)).to(DEV)
-    rep = net.fit(X, Yn, int(0.9 * X.shape[0]), epochs=15, batch=128, lr=2e-3, lr_final=1e-5)
+    rep = net.fit(X, Yn, int(0.9 * X.shape[0]), epochs=30, batch=256, lr=2e-3, lr_final=1e-5)
     print(f"\ntrained in {rep.seconds:.1f} s, val mse {rep.val_loss[0]:.3e} -> {rep.val_loss[-1]:.3e}", flush=True)
     osys = oracle.System.from_ybus(yb, g.bus_type)
     ro = osys.solve(ev.sbus, ev.v0)

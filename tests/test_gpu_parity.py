@@ -219,8 +219,15 @@ def test_full_set_fp64_matches_oracle(systems, key, name):
     rg = pf.solve_batch(plan, y, s, v)
     torch.cuda.synchronize()
     bl = compare_solve(osys, ro, rg, sc.sbus)
-    print(f"{key}: {len(bl)} borderline instances; converged {rg.converged.float().mean().item():.5f}")
-    assert len(bl) <= sc.batch // 100
+    it_g = rg.iters.cpu().numpy()
+    both = rg.converged.cpu().numpy().astype(bool) & ro.converged
+    differ = np.flatnonzero(both & (it_g != ro.iters))
+    print(f"{key}: {len(bl)} borderline instances (oracle's final or penultimate max|F| within a factor 2 "
+          f"of tol), {differ.size} of them stop at another iteration; converged "
+          f"{rg.converged.float().mean().item():.5f}")
+    # only instances whose mismatch lands within rounding of the tolerance may stop at
+    # another iteration (compare_solve checked they are valid); such ties are rare
+    assert differ.size <= max(2, sc.batch // 1000), differ[:20]
     assert rg.converged.float().mean().item() > 0.99
 
 
@@ -459,3 +466,38 @@ def test_host_resident_pipelined_solve_matches_device_solve(systems):
     assert torch.equal(r.v, d.v.cpu())
     assert torch.equal(r.iters, d.iters.cpu()) and torch.equal(r.converged, d.converged.cpu())
     assert torch.equal(r.status, d.status.cpu())
+
+
+@pytest.mark.parametrize("prec", [pf.PF_FP64, pf.PF_FP32_LU])
+def test_zero_pivot_instances_rescued_by_fallback(prec):
+    """Half of a batch carries a Ybus whose first pre-order bus hangs on purely resistive
+    branches (its first pivot is exactly zero at flat start), the other half the original
+    values.  The GPU refactorization reports PF_ST_PIVOT for exactly the first half;
+    pf_solve_fallback re-solves those with the threshold-pivoting factorization, and every
+    instance then meets the FP64 full-solve bar against the oracle (the oracle pivots)."""
+    from tests.test_fallback import resistive_first_bus
+    g2, yb2, plan, _ = resistive_first_bus("c4_100bus")
+    g = gg.grid("c4_100bus")
+    yb = gg.ybus(g)
+    B = 32
+    sc = gg.make_scenarios(g2, B, 77, "mc")
+    yv = np.stack([yb2.val if b < B // 2 else yb.val for b in range(B)])
+    y = torch.from_numpy(yv).to(DEV)
+    s = torch.from_numpy(np.ascontiguousarray(sc.sbus)).to(DEV)
+    v = torch.from_numpy(np.ascontiguousarray(sc.v0)).to(DEV)
+    r = pf.solve_batch(plan, y, s, v, precision=prec)
+    torch.cuda.synchronize()
+    st = r.status.cpu().numpy()
+    assert (st[:B // 2] == pf.PF_ST_PIVOT).all(), st
+    assert (st[B // 2:] == pf.PF_ST_CONVERGED).all(), st
+    r2 = pf.solve_batch(plan, y, s, v, precision=prec, pivot_fallback=True)
+    assert r2.n_resolved == B // 2
+    for half, ybv in ((slice(0, B // 2), yb2), (slice(B // 2, B), yb)):
+        osys = oracle.System.from_ybus(ybv, g.bus_type)
+        ro = osys.solve(sc.sbus[half], sc.v0[half])
+        assert ro.converged.all()
+        sub = pf.Result(v=r2.v[half], iters=r2.iters[half], converged=r2.converged[half], status=r2.status[half])
+        if prec == pf.PF_FP64 or half.start == 0:
+            compare_solve(osys, ro, sub, sc.sbus[half])
+        else:
+            compare_fp32lu(osys, ro, sub, sc.sbus[half])

@@ -240,7 +240,11 @@ def test_queue_four_grid_mix_matches_oracle(prec):
         osys, ro = oracle_solution(name, sc)
         if prec == pf.PF_FP64:
             bl = compare_solve(osys, ro, out, sc.sbus)
-            assert len(bl) <= max(2, sc.batch // 100), (name, len(bl))
+            it_g = out.iters.cpu().numpy()
+            both = out.converged.cpu().numpy().astype(bool) & ro.converged
+            differ = np.flatnonzero(both & (it_g != ro.iters))
+            print(f"{name}: {len(bl)} borderline, {differ.size} stop at another iteration", flush=True)
+            assert differ.size <= max(2, sc.batch // 1000), (name, differ[:20])
         else:
             compare_fp32lu(osys, ro, out, sc.sbus, name=name)
         assert out.converged.float().mean().item() > 0.99, name
