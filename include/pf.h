@@ -185,6 +185,23 @@ int pf_solve_batch(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus
  *                     order (so that V_new = V - dx).
  */
 /*
+ * pf_solve_batch_noalloc: pf_solve_batch without a workspace argument and without any
+ * device allocation, for callers that cannot allocate (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  The workspace is a fixed 128 MiB
+ * device array inside the library (one per device, held until the process ends); a call
+ * whose pf_workspace_bytes(plan, batch, opts) exceeds it fails with PF_EINVAL and a
+ * message, so split larger batches.  The plan must already be resident on the current
+ * device (pf_analyze uploads it when a device is present), otherwise PF_EINVAL.  Same
+ * kernels, inputs, outputs, stream ordering and results as pf_solve_batch.  Every call
+ * on one device shares that array: calls that overlap in time on one device (two streams,
+ * two threads) race and must be serialised by the caller.
+ */
+int pf_solve_batch_noalloc(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus_batched,
+                           const double *sbus, const double *v0, double tol, int32_t max_iter,
+                           const pf_solve_opts *opts, double *v_out, int32_t *iters_out, uint8_t *converged_out,
+                           int8_t *status_out, void *stream);
+
+/*
  * pf_solve_batch_warm: pf_solve_batch from the start v0 (e.g. a learned prediction) with
  * an in-kernel fallback: an instance whose attempt from v0 fails (non-finite mismatch, an
  * update that does not reduce max|F|, or a zero pivot) restarts once from v_fallback

@@ -29,7 +29,8 @@ EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
             "pf_mlp_features", "pf_mlp_warm_v0", "pf_queue_create", "pf_queue_add",
             "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune", "pf_solve_batch_warm",
             "pf_resolve_opts", "pf_branch_flows", "pf_plan_schedule", "pf_solve_host",
-            "pf_plan_levels", "pf_cpu_solve_batch", "pf_cpu_solve_pivoting", "pf_solve_fallback"]
+            "pf_plan_levels", "pf_cpu_solve_batch", "pf_cpu_solve_pivoting", "pf_solve_fallback",
+            "pf_solve_batch_noalloc"]
 
 
 class PfError(RuntimeError):
@@ -84,6 +85,8 @@ def lib():
                                             ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp]
         L.pf_solve_fallback.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_double,
                                         ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _i32p, _vp]
+        L.pf_solve_batch_noalloc.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_double,
+                                             ctypes.c_int32, ctypes.POINTER(_Opts), _vp, _vp, _vp, _vp, _vp]
         L.pf_plan_lu_pattern.argtypes = [_vp, _i32p, _i32p, _i32p]
         L.pf_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_Opts)]
         L.pf_workspace_bytes.restype = ctypes.c_size_t
@@ -330,6 +333,26 @@ def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 1
                                      ctypes.byref(nr), _stream_ptr(stream))
         _check(rc, "pf_solve_fallback")
         out.n_resolved = int(nr.value)
+    return out
+
+
+def solve_batch_noalloc(plan: Plan, ybus, sbus, v0, out: Result, tol: float = 1e-8, max_iter: int = 10,
+                        precision: int = PF_FP64, tile: int = 0, waves: int = 0, schedule: int = 0,
+                        long_slots: int = 0, stream=None) -> Result:
+    """pf_solve_batch_noalloc: pf_solve_batch into the caller's `out` tensors, with the
+    library's fixed device scratch as workspace (no allocation by the library or here)."""
+    torch = _torch()
+    B = int(v0.shape[0])
+    yp, _, yb_batched = _ybus_view(plan, ybus, B)
+    s2 = _as_pairs(sbus, "sbus")
+    sp = _dev_ptr(s2, torch.float64, (B, plan.n, 2), "sbus")
+    vp = _dev_ptr(v0, torch.float64, (B, plan.n, 2), "v0")
+    outs = (_dev_ptr(out.v, torch.float64, (B, plan.n, 2), "v_out"), _dev_ptr(out.iters, torch.int32, (B,), "iters"),
+            _dev_ptr(out.converged, torch.uint8, (B,), "converged"), _dev_ptr(out.status, torch.int8, (B,), "status"))
+    opts = _Opts(precision, tile, waves, schedule, long_slots)
+    rc = lib().pf_solve_batch_noalloc(plan._h, B, yp, yb_batched, sp, vp, float(tol), int(max_iter),
+                                      ctypes.byref(opts), *outs, _stream_ptr(stream))
+    _check(rc, "pf_solve_batch_noalloc")
     return out
 
 

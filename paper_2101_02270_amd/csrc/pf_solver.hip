@@ -1141,6 +1141,39 @@ static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *
     return PF_OK;
 }
 
+// ------------------------------------------------------------------ fixed scratch
+// The workspace of pf_solve_batch_noalloc: a file-scope device array, so that a caller that
+// cannot allocate (graph capture, serving loops) still gets a solve.  Each device holds its
+// own copy at its own address, looked up once per device with hipGetSymbolAddress; host
+// code passes that address, never the array's name.  No part of it needs clearing: the
+// kernel writes every word of a tile's block before reading it.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static int scratch_address(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        set_error("no usable HIP device for the fixed scratch");
+        return PF_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error(std::string("hipGetSymbolAddress of the fixed scratch failed: ") + hipGetErrorString(e));
+            return PF_EDEVICE;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PF_OK;
+}
+
 // ------------------------------------------------------------------ plan upload
 // Zero padding after the tables the kernels read in whole chunks, so that those loads
 // need no bounds guard (a guarded load becomes a masked load plus a register copy, and the
@@ -1610,6 +1643,33 @@ int pf_solve_batch(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus
     if (ybus_batched != 0 && ybus_batched != 1) { set_error("ybus_batched must be 0 or 1"); return PF_EINVAL; }
     return run(plan, batch, ybus, sbus, v0, tol, max_iter, opts, workspace, workspace_bytes, MODE_SOLVE,
                v_out, iters_out, converged_out, status_out, nullptr, nullptr, stream, nullptr, ybus_batched);
+}
+
+int pf_solve_batch_noalloc(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus_batched,
+                           const double *sbus, const double *v0, double tol, int32_t max_iter,
+                           const pf_solve_opts *opts, double *v_out, int32_t *iters_out, uint8_t *converged_out,
+                           int8_t *status_out, void *stream)
+{
+    if (ybus_batched != 0 && ybus_batched != 1) { set_error("ybus_batched must be 0 or 1"); return PF_EINVAL; }
+    Plan *pl = reinterpret_cast<Plan *>(plan);
+    if (!pl) { set_error("null plan"); return PF_EINVAL; }
+    if (batch < 0) { set_error("negative batch"); return PF_EINVAL; }
+    if (batch == 0) return PF_OK;
+    // the plan must already be resident: uploading it here would allocate
+    if (!pl->dev_mem) { set_error("the plan is not resident on a device (pf_analyze found none)"); return PF_EINVAL; }
+    const size_t need = pf_workspace_bytes(plan, batch, opts);
+    if (need == 0) return PF_EINVAL;   // pf_workspace_bytes set the message
+    if (need > kScratchBytes) {
+        set_error("pf_solve_batch_noalloc: " + std::to_string(batch) + " instances need " + std::to_string(need) +
+                  " bytes of scratch, more than its fixed " + std::to_string(kScratchBytes) +
+                  " bytes; use fewer instances per call or pf_solve_batch with a workspace");
+        return PF_EINVAL;
+    }
+    void *ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc != PF_OK) return rc;
+    return run(plan, batch, ybus, sbus, v0, tol, max_iter, opts, ws, kScratchBytes, MODE_SOLVE, v_out, iters_out,
+               converged_out, status_out, nullptr, nullptr, stream, nullptr, ybus_batched);
 }
 
 int pf_solve_batch_warm(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus_batched,
