@@ -202,10 +202,14 @@ def grid9000_variant(steps, warmup, log):
     y = torch.from_numpy(yb.val).to(dev)
     s = torch.from_numpy(np.ascontiguousarray(sc.sbus)).to(dev)
     v = torch.from_numpy(np.ascontiguousarray(sc.v0)).to(dev)
+    cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
-    ro = oracle.System.from_ybus(yb, g.bus_type).solve(sc.sbus, sc.v0, threads=len(os.sched_getaffinity(0)))
-    log(f"[bench] 9000-bus oracle reference solved in {time.perf_counter() - t0:.1f} s")
-    out = {"workload": WORKLOADS["c2"]["desc"], "stress_factor": g.scale, "batch": sc.batch}
+    ro = oracle.System.from_ybus(yb, g.bus_type).solve(sc.sbus, sc.v0, threads=cores)
+    dt_o = time.perf_counter() - t0
+    log(f"[bench] 9000-bus oracle reference solved in {dt_o:.1f} s")
+    out = {"workload": WORKLOADS["c2"]["desc"], "stress_factor": g.scale, "batch": sc.batch,
+           "cpu_oracle": {"value": round(int(ro.converged.sum()) / dt_o, 1), "unit": "flows/s", "cores": cores,
+                          "sample": f"all {sc.batch} scenarios once (the parity reference), {dt_o:.1f} s"}}
     its = {}
     for prec, name in ((pf.PF_FP64, "fp64"), (pf.PF_FP32_LU, "fp32lu")):
         ws = torch.empty(plan.workspace_bytes(sc.batch, prec) + 256, dtype=torch.uint8, device=dev)
@@ -484,6 +488,7 @@ def main():
     torch.cuda.synchronize()
     analyze_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info
+    launch = plan.resolve(sc.batch, prec, args.tile, args.waves)["launch"]
 
     y = torch.from_numpy(yb.val).to(dev)
     s = torch.from_numpy(np.ascontiguousarray(sc.sbus)).to(dev)
@@ -540,7 +545,8 @@ def main():
         "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "batch": B, "n_bus": g.n, "precision": args.precision,
-                   "start": "flat", "tol": tol, "max_iter": max_iter, "stress_factor": g.scale},
+                   "start": "flat", "tol": tol, "max_iter": max_iter, "stress_factor": g.scale,
+                   "launch": "fused" if launch == pf.PF_LAUNCH_FUSED else "per-phase"},
         "converged_fraction": round(n_conv / B, 5),
         "status": status_histogram(out.status.cpu().numpy()),
         "iterations_mean": round(float(iters[conv].mean()) if n_conv else 0.0, 4),
@@ -550,7 +556,9 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": (measured_traffic() if (args.workload == "c1" and not fp32 and not args.tile
                                                         and not args.waves and not args.count) else None),
-                     "kernel": "nr_tile_kernel", "kernel_ms": round(kernel_ms, 4),
+                     "kernel": ("nr_tile_kernel (one launch per solve)" if launch == pf.PF_LAUNCH_FUSED else
+                                "per-phase launches of one solve (split_v/m/lu/bs_kernel)"),
+                     "kernel_ms": round(kernel_ms, 4),
                      "algorithmic_bytes_per_launch": abytes},
     }
     log = lambda m: print(m, file=sys.stderr, flush=True)

@@ -78,8 +78,15 @@ typedef struct {
                               info.slot_rows (1..12): more let more of the serial tail of the
                               elimination overlap, at the cost of LDS; 0 = automatic (the
                               most that keep the resident workgroups the batch can use)    */
-    int32_t reserved[3];
+    int32_t launch;        /* PF_LAUNCH_AUTO (0), PF_LAUNCH_FUSED (1): one launch runs every
+                              Newton iteration of a tile; PF_LAUNCH_PHASES (2): one launch per
+                              phase and iteration (mismatch/Jacobian over all buses and
+                              instances, refactorization per tile, back substitution per
+                              tile), each with its own register budget.  Same results.
+                              pf_solve_batch only; the other entry points run fused        */
+    int32_t reserved[2];
 } pf_solve_opts;
+enum { PF_LAUNCH_AUTO = 0, PF_LAUNCH_FUSED = 1, PF_LAUNCH_PHASES = 2 };
 
 /*
  * pf_analyze -- one-time analysis of a Ybus pattern (Sec. 4.1: pre-order, symbolic LU
@@ -137,6 +144,20 @@ int pf_plan_schedule(pf_plan plan, int32_t order, int32_t *first, int32_t *width
 
 /* Workspace bytes pf_solve_batch needs for `batch` instances with `opts` (NULL = default). */
 size_t pf_workspace_bytes(pf_plan plan, int32_t batch, const pf_solve_opts *opts);
+
+/*
+ * pf_plan_ring: where the refactorization keeps the working columns of each long panel
+ * (more than slot_rows rows) for panel order `order` (0 level, 1 elimination) and an LDS
+ * budget of n_long (1..12) pairs of max_col rows: an LDS ring of n_long * 2 * max_col
+ * rows, handed out in rank order, wrapping to row 0 when a panel does not fit before the
+ * end.  For each long rank r (0 .. n_long_panels - 1): offset[r] its first row, rows[r]
+ * its row count (one column, or both columns of a pair), and the rank range
+ * wait_lo[r] .. wait_hi[r] of earlier long panels that last held any of those rows and
+ * must have published before it starts (empty when wait_lo > wait_hi).  Host arrays of
+ * n_long_panels entries; PF_EINVAL for invalid arguments.
+ */
+int pf_plan_ring(pf_plan plan, int32_t order, int32_t n_long, int32_t *offset, int32_t *rows, int32_t *wait_lo,
+                 int32_t *wait_hi);
 
 /*
  * pf_resolve_opts: the configuration pf_solve_batch would use for batch instances with opts
@@ -312,7 +333,8 @@ void pf_queue_destroy(pf_queue queue);
 /*
  * pf_tune: times every configuration (tile, waves, schedule, and long slots: the automatic
  * count for this batch and 2, 4, 8, each distinct count once) that fits in LDS on the given
- * instances (the same arguments as pf_solve_batch) with reps timed solves after one
+ * instances (the same arguments as pf_solve_batch), in the single-launch form the queue
+ * runs (launch = PF_LAUNCH_FUSED in best_out), with reps timed solves after one
  * untimed one, and returns the one with the most converged flows per second in best_out
  * (its mean ms per solve in best_ms_out, may be NULL).  A candidate whose untimed solve
  * converges fewer instances than the default configuration's, or reports PF_ST_INTERNAL,

@@ -46,6 +46,16 @@ struct BsPanel {
 };
 
 
+// Most shared long working-column slots of a launch: the LDS budget of the long panels is
+// n_long (1..kMaxLong) times a pair of columns of max_col rows.
+constexpr int kMaxLong = 12;
+
+// A long panel's place in the LDS ring (see HostPlan::ring): its first row, and the range
+// lo (bits 0-15) .. hi (bits 16-31) of earlier long ranks it waits for (lo > hi: none).
+struct RingSlot {
+    int32_t off, blk;
+};
+
 // Everything pf_analyze derives from the pattern, on the host.
 struct HostPlan {
     int n = 0, nnzy = 0, npv = 0, npq = 0, npvpq = 0, N = 0, ref = -1;
@@ -79,16 +89,23 @@ struct HostPlan {
     // processing orders of the panels: by refactorization level (a topological order of
     // the column DAG) and by back-substitution level (topological for the row DAG)
     std::vector<int32_t> lu_seq, bs_seq;
-    // working-column slots of the refactorization: a panel of at most slot_rows rows uses
-    // its wavefront's own slot; a longer panel uses one of the launch's L shared slots (L
-    // is chosen per launch from the LDS left over).  For each of the two panel orders
-    // (level, elimination): the rank of each panel among the order's long panels (-1 for
-    // a short panel) and the first column of the long panel of each rank.  The long panel
-    // of rank r takes slot r mod L once the one of rank r - L has published, so slots are
-    // handed out in topological order.
+    // working columns of the refactorization: a panel of at most slot_rows rows uses its
+    // wavefront's own pair of short columns; a longer panel takes rows of the launch's
+    // shared LDS ring (its budget is chosen per launch from the LDS left over).  For each
+    // of the two panel orders (level, elimination): the rank of each panel among the
+    // order's long panels (-1 for a short panel) and the first column of the long panel of
+    // each rank; ranks follow the order, so the ring is handed out in topological order.
     int slot_rows = 0, n_longp = 0;
     std::vector<int32_t> long_rank;               // [2][n_panels]
     std::vector<int32_t> long_first;              // [2][n_longp]
+    // The long panels' working columns are packed into an LDS ring of n_long * 2 * max_col
+    // rows, each panel taking exactly its own rows (one column, or both of a pair), handed
+    // out in rank order and wrapping to the start when the end is reached.  For each
+    // budget n_long, order and rank: the panel's first row in the ring and the range of
+    // earlier ranks (lo, hi) whose rows it reuses; it starts once every rank in that range
+    // has published.  ring[((n_long - 1) * 2 + order) * n_longp + rank] = {offset,
+    // lo | hi << 16}, lo > hi when no rank precedes it there.
+    std::vector<RingSlot> ring;                   // [kMaxLong][2][n_longp]
     // per order (0: level, 1: elimination) and position in that order
     std::vector<LuPanel> lu_desc;                 // [2][n_panels]
     std::vector<BsPanel> bs_desc;                 // [2][n_panels]
@@ -111,7 +128,8 @@ struct DevPlan {
     const int32_t *bus_peq, *bus_qeq;
     const LuPanel *lu_desc;
     const BsPanel *bs_desc;
-    int n_panels, slot_rows;
+    const RingSlot *ring;
+    int n_panels, slot_rows, n_longp;
 };
 
 struct Plan {

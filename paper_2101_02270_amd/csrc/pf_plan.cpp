@@ -376,6 +376,33 @@ int analyze(int n, int nnzy, const int32_t *row_ptr, const int32_t *col_idx,
                 r++;
             }
         }
+        if (h.n_longp >= (1 << 15)) { err = "too many long panels"; return PF_EINVAL; }
+        // the LDS ring of the long panels, for every budget: rows are handed out in rank
+        // order; a panel that does not fit before the end starts again at row 0; the ranks
+        // that last held any of its rows must have published before it starts
+        h.ring.assign((size_t)kMaxLong * 2 * h.n_longp, RingSlot{0, 1});
+        std::vector<int> last;
+        for (int nl = 1; nl <= kMaxLong; nl++) {
+            const int cap = nl * 2 * h.max_col;
+            for (int order = 0; order < 2; order++) {
+                last.assign(cap, -1);
+                int at = 0;
+                for (int r = 0; r < h.n_longp; r++) {
+                    const int j = h.long_first[(size_t)order * h.n_longp + r];
+                    const int w = *std::upper_bound(h.panel_ptr.begin(), h.panel_ptr.end(), j) - j;
+                    const int size = w * (h.col_ptr[j + 1] - h.col_ptr[j]);
+                    if (at + size > cap) at = 0;
+                    int lo = h.n_longp, hi = -1;
+                    for (int u = at; u < at + size; u++) {
+                        if (last[u] >= 0) { lo = std::min(lo, last[u]); hi = std::max(hi, last[u]); }
+                        last[u] = r;
+                    }
+                    if (hi < 0) { lo = 1; hi = 0; }
+                    h.ring[(((size_t)nl - 1) * 2 + order) * h.n_longp + r] = RingSlot{at, lo | (hi << 16)};
+                    at += size;
+                }
+            }
+        }
     }
 
     // ---- per-position panel descriptors of both orders

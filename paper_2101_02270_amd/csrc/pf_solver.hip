@@ -47,9 +47,10 @@ void set_error(const std::string &msg) { g_err = msg; }
 
 enum Mode { MODE_SOLVE = 0, MODE_MISMATCH = 1, MODE_FACTOR = 2, MODE_STEP = 3 };
 
+constexpr int kMBlock = 256;     // threads of a mismatch-kernel workgroup (per-phase launches)
+constexpr size_t kBsZBytes = 48 * 1024;   // per-phase back substitution: LDS for z of the tail
 constexpr int UPD_GROUP = 3;     // column updates whose operand loads are issued together
 constexpr int L_ROWS = 2;        // rows of each source column per lane loaded with its group
-constexpr int kMaxLong = 12;     // most shared long working-column slots of a launch
 
 struct KArgs {
     DevPlan p;
@@ -61,10 +62,11 @@ struct KArgs {
     const double *v_fb;         // [B][n][2] restart point after a failed first attempt (may be null)
     double tol;
     int max_iter, batch, mode;
-    int n_long;                 // shared long working-column slots of the refactorization
-    unsigned n_long_inv;        // ceil(2^32 / n_long) for n_long >= 2
+    int n_long;                 // LDS budget of the long panels' ring, in pairs of max_col rows
     char *ws;
     size_t tile_bytes, off_y, off_vec;   // byte offsets inside one tile's block
+    size_t off_ctl, off_part;   // per-phase launches: instance states and tile flags; mismatch maxima
+    int nbb;                    // per-phase launches: bus blocks of the mismatch kernel
     double *v_out;
     int32_t *iters_out;
     uint8_t *conv_out;
@@ -169,6 +171,599 @@ __device__ __forceinline__ void note_progress(int *prog, int wave, int &count)
     __hip_atomic_store(&prog[wave], ++count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Per-tile state shared by the phases of the Newton loop: the tile's arrays, the LDS
+// working areas and flags, and the lane's place in the workgroup.
+template <typename R>
+struct TileCtx {
+    const KArgs &a;
+    int tid, wave, lane, t, s;
+    bool valid;
+    R *LU, *Yv;
+    double *Vm, *Va;
+    R *short_base, *long_base, *ysl, *ysl1, *cmx, *cmx1;
+    unsigned char *done, *ldone;
+    int *err, *s_prog, *s_piv;
+    const int *s_active, *s_reset;
+    int &nprog;                         // this wavefront's publications so far
+    R *zlds;                            // back substitution: z of positions >= zb in LDS
+    int zb;                             // (zb = N: none)
+};
+
+// ---- refactorization with the forward substitution carried along (Sec. 4.2-4.3): the
+// Jacobian values are in the tile's LU array and the right-hand sides in Yv; on return every
+// panel has published (or the tile's error flag is set) and s_piv marks failed pivots.
+// WIDE: the per-phase kernel, which has registers to spare, keeps more loads in flight
+// (four rows per sub-lane per round trip for a long panel's own rows and for a source
+// column's rows beyond the group load); the fused kernel is at its register limit.
+template <typename R, int T, int NW, bool WIDE>
+__device__ __forceinline__ void lu_phase(TileCtx<R> &cx)
+{
+    constexpr int SL = 64 / T;
+    constexpr int NT = NW * 64;
+    constexpr int A_ROWS = 2;            // panel rows per lane whose loads are issued together
+    const KArgs &a = cx.a;
+    const DevPlan &P = a.p;
+    const int tid = cx.tid, wave = cx.wave, lane = cx.lane, t = cx.t, s = cx.s;
+    const bool valid = cx.valid;
+    const int N = P.N;
+    R *const LU = cx.LU;
+    R *const Yv = cx.Yv;
+    R *const short_base = cx.short_base, *const long_base = cx.long_base;
+    R *const ysl = cx.ysl, *const ysl1 = cx.ysl1, *const cmx = cx.cmx, *const cmx1 = cx.cmx1;
+    unsigned char *const done = cx.done, *const ldone = cx.ldone;
+    int *const err = cx.err, *const s_prog = cx.s_prog, *const s_piv = cx.s_piv;
+    int &nprog = cx.nprog;
+    for (int w = tid; w < N + P.n_longp; w += NT)
+        __hip_atomic_store(&done[w], (unsigned char)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();
+    // Panels (one column, or the angle/|V| pair of a PQ bus sharing one row list) in
+    // level order, round-robin over the wavefronts.  The order is topological, so the
+    // earliest unfinished panel always has every source published and some wavefront
+    // always makes progress; level order keeps independent panels side by side.
+    // The loads of a panel's Jacobian values and right-hand sides do not depend on any
+    // other panel (only the panel itself rewrites its columns and rows), so they are
+    // software-pipelined: while a wavefront works on one panel, the loads of its next
+    // panel are in flight.  A_ROWS rows per lane travel this way; longer panels load
+    // their remaining rows when they start.
+    //
+    // Metadata travels in vector registers instead of scalar loads (a scalar load is
+    // counted together with LDS operations, so every LDS wait would also wait for it):
+    // one load brings the descriptors of the wavefront's next 8 panels (lane l holds
+    // word l % 8 of descriptor l / 8) and one load 16 update records of a panel (lane l
+    // holds word l % 4 of record l / 4); fields are read with readlane.  A panel's first
+    // 16 records arrive with its prefetch; a panel with more loads each further chunk
+    // one chunk ahead of its use, so no update group waits for its own records.
+    const LuPanel *lud = P.lu_desc + (size_t)a.sched * P.n_panels;
+    auto desc_chunk = [&](int c) -> int {
+        const int qq = wave + NW * (8 * c + (lane >> 3));
+        return reinterpret_cast<const int *>(lud)[(size_t)qq * 8 + (lane & 7)];   // padded table
+    };
+    auto desc_from = [&](int chunk, int k) -> LuPanel {
+        LuPanel d;
+        int *w = reinterpret_cast<int *>(&d);
+#pragma unroll
+        for (int f = 0; f < 8; f++) w[f] = __builtin_amdgcn_readlane(chunk, k * 8 + f);
+        return d;
+    };
+    // records [ua, ua + 16); only those below the panel's end are read back (the table
+    // is padded by one chunk)
+    auto upd_chunk_at = [&](int ua) -> int { return reinterpret_cast<const int *>(P.upd)[(size_t)ua * 4 + lane]; };
+    auto upd_chunk = [&](const LuPanel &d) -> int { return upd_chunk_at(d.u0); };
+    R pa0[A_ROWS], pa1[A_ROWS], py0 = 0, py1 = 0;
+    unsigned char pf[A_ROWS];
+    int pupd = 0;
+    auto prefetch = [&](const LuPanel &d) {
+        pupd = upd_chunk(d);
+        const int jn = d.j2 & ((1 << 30) - 1);
+        const bool tw = (d.j2 >> 30) & 1;
+#pragma unroll
+        for (int r = 0; r < A_ROWS; r++) {
+            const int e = min(s + r * SL, d.cnt - 1);      // rows past the end re-read the last
+            pf[r] = P.isj[d.cs + e];
+            pa0[r] = LU[(size_t)(d.cs + e) * T + t];
+            pa1[r] = LU[(size_t)(d.cs + (tw ? d.cnt : 0) + e) * T + t];
+        }
+        py0 = Yv[jn * T + t];
+        py1 = Yv[(jn + (tw ? 1 : 0)) * T + t];
+    };
+    int dch0 = desc_chunk(0), dch1 = desc_chunk(1);
+    LuPanel pdc = desc_from(dch0, 0);         // the current panel's descriptor, kept in
+    if (wave < P.n_panels) prefetch(pdc);     // scalar registers across iterations
+    wait_loads_returned();
+    for (int q = wave, qi = 0; q < P.n_panels; q += NW, qi++) {
+        const int kq = qi & 7;
+        const LuPanel pd = pdc;
+        const int ucur = pupd;
+        const int j = pd.j2 & ((1 << 30) - 1);
+        const bool two = (pd.j2 >> 30) & 1;
+        const int cs = pd.cs, cnt = pd.cnt, dr = pd.dr;
+        const bool more = q + NW < P.n_panels;
+        const LuPanel pdn = kq < 7 ? desc_from(dch0, kq + 1) : desc_from(dch1, 0);
+        if (kq == 7) {
+            dch0 = dch1;
+            dch1 = desc_chunk((qi >> 3) + 2);
+        }
+        R *xw, *xw1;
+        if (pd.lrank < 0) {
+            xw = short_base + (size_t)wave * 2 * P.slot_rows * T;
+            xw1 = xw + (size_t)P.slot_rows * T;
+        } else {
+            // a long panel takes its own rows of the ring once every earlier long panel
+            // that last held any of them has published (ranks follow the topological
+            // order); the entry is read with a per-lane address so that it is a vector
+            // load (a scalar load would share its counter with the LDS operations)
+            const int rw = reinterpret_cast<const int *>(
+                P.ring + ((size_t)(a.n_long - 1) * 2 + a.sched) * P.n_longp + pd.lrank)[lane & 1];
+            const int roff = __builtin_amdgcn_readlane(rw, 0), rblk = __builtin_amdgcn_readlane(rw, 1);
+            for (int rr = rblk & 0xffff; rr <= (rblk >> 16); rr++) wait_published<NW>(ldone, rr, s_prog, err);
+            xw = long_base + (size_t)roff * T;
+            xw1 = xw + (size_t)cnt * T;
+        }
+        // the panel's Jacobian values (written by the mismatch pass; fill positions read
+        // as zero; both columns of a pair share the row list and the fill pattern) and
+        // right-hand sides
+        {
+            R cm0 = 0, cm1 = 0;
+#pragma unroll
+            for (int r = 0; r < A_ROWS; r++) {
+                const int e = s + r * SL;
+                if (e < cnt) {
+                    const R a0 = pf[r] ? pa0[r] : (R)0, a1 = pf[r] ? pa1[r] : (R)0;
+                    xw[e * T + t] = a0;
+                    if (two) xw1[e * T + t] = a1;
+                    cm0 = fmax(cm0, fabs(a0));
+                    cm1 = fmax(cm1, fabs(a1));
+                }
+            }
+            if (s == 0) {
+                ysl[t] = py0;
+                if (two) ysl1[t] = py1;
+            }
+            if constexpr (WIDE) {
+                // rows past the end read the following entries of the tile's block and the
+                // padded flag table, and are discarded
+                for (int e0 = s + A_ROWS * SL; e0 < cnt; e0 += 4 * SL) {
+                    R v0[4], v1[4];
+                    bool fe[4];
+#pragma unroll
+                    for (int x = 0; x < 4; x++) {
+                        const int e = e0 + x * SL;
+                        fe[x] = P.isj[cs + e];
+                        v0[x] = LU[(size_t)(cs + e) * T + t];
+                        v1[x] = LU[(size_t)(cs + (two ? cnt : 0) + e) * T + t];
+                    }
+#pragma unroll
+                    for (int x = 0; x < 4; x++) {
+                        const int e = e0 + x * SL;
+                        if (e < cnt) {
+                            const R a0 = fe[x] ? v0[x] : (R)0, a1 = fe[x] ? v1[x] : (R)0;
+                            xw[e * T + t] = a0;
+                            if (two) xw1[e * T + t] = a1;
+                            cm0 = fmax(cm0, fabs(a0));
+                            cm1 = fmax(cm1, fabs(a1));
+                        }
+                    }
+                }
+            } else {
+                for (int e = s + A_ROWS * SL; e < cnt; e += SL) {
+                    const bool fe = P.isj[cs + e];
+                    const R v0 = LU[(size_t)(cs + e) * T + t];
+                    const R v1 = two ? LU[(size_t)(cs + cnt + e) * T + t] : (R)0;
+                    const R a0 = fe ? v0 : (R)0, a1 = fe ? v1 : (R)0;
+                    xw[e * T + t] = a0;
+                    if (two) xw1[e * T + t] = a1;
+                    cm0 = fmax(cm0, fabs(a0));
+                    cm1 = fmax(cm1, fabs(a1));
+                }
+            }
+            // the column maxima over the instance's sub-lanes, kept in LDS until the pivots
+#pragma unroll
+            for (int off = T; off < 64; off <<= 1) {
+                cm0 = fmax(cm0, __shfl_xor(cm0, off));
+                cm1 = fmax(cm1, __shfl_xor(cm1, off));
+            }
+            if (s == 0) {
+                cmx[t] = cm0;
+                cmx1[t] = cm1;
+            }
+        }
+        if (more) prefetch(pdn);
+        pdc = pdn;
+        // Updates in ascending source order.  After waiting for the first pending source,
+        // the run of following updates whose sources are already published (up to
+        // UPD_GROUP, within one chunk of records) has its operand loads issued together
+        // (L_ROWS rows of each source column per lane), then the updates are applied one
+        // after another in LDS (the order of the arithmetic is unchanged).  Rows beyond
+        // L_ROWS per lane (the long source columns of the dense tail) are loaded two at a
+        // time.
+        const int u0 = pd.u0, u1 = pd.u1;
+        int ubase = u0, uc0 = ucur, uc1 = 0;
+        if (u1 - u0 > 16) uc1 = upd_chunk_at(u0 + 16);
+        auto upd_rec = [&](int u) -> Update {
+            const int r = u - ubase;
+            Update x;
+            x.krel_lcnt = __builtin_amdgcn_readlane(uc0, 4 * r);
+            x.lbeg = __builtin_amdgcn_readlane(uc0, 4 * r + 1);
+            x.roff = __builtin_amdgcn_readlane(uc0, 4 * r + 2);
+            x.k = __builtin_amdgcn_readlane(uc0, 4 * r + 3);
+            return x;
+        };
+        for (int ub = u0; ub < u1;) {
+            if (ub - ubase >= 16) {
+                ubase += 16;
+                uc0 = uc1;
+                if (u1 - ubase > 16) uc1 = upd_chunk_at(ubase + 16);
+            }
+            Update ups[UPD_GROUP];
+            ups[0] = upd_rec(ub);
+            wait_published<NW>(done, ups[0].k, s_prog, err);
+            int gcnt = 1;
+#pragma unroll
+            for (int g = 1; g < UPD_GROUP; g++) {
+                if (gcnt == g && ub + g < u1 && ub + g - ubase < 16) {
+                    ups[g] = upd_rec(ub + g);
+                    const int f = __builtin_amdgcn_readfirstlane((int)__hip_atomic_load(
+                        &done[ups[g].k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                    if (f) gcnt = g + 1;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            R lv[UPD_GROUP][L_ROWS], yk[UPD_GROUP];
+            int rv[UPD_GROUP][L_ROWS];
+#pragma unroll
+            for (int g = 0; g < UPD_GROUP; g++) {
+                yk[g] = 0;
+#pragma unroll
+                for (int e = 0; e < L_ROWS; e++) { lv[g][e] = 0; rv[g][e] = -1; }
+                if (g < gcnt) {
+                    const int lcnt = ups[g].krel_lcnt >> 16;
+#pragma unroll
+                    for (int e = 0; e < L_ROWS; e++)
+                        if (s + e * SL < lcnt) {
+                            lv[g][e] = LU[(size_t)(ups[g].lbeg + s + e * SL) * T + t];
+                            rv[g][e] = P.rel[ups[g].roff + s + e * SL];
+                        }
+                    yk[g] = Yv[ups[g].k * T + t];
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int g = 0; g < UPD_GROUP; g++) {
+                if (g < gcnt) {
+                    const Update up = ups[g];
+                    const int krel = up.krel_lcnt & 0xffff, lcnt = up.krel_lcnt >> 16;
+                    const R m0 = xw[krel * T + t];
+                    const R m1 = two ? xw1[krel * T + t] : (R)0;
+                    const R ykg = yk[g];
+                    // row tr of the panel's columns (and its right-hand side) minus the
+                    // multipliers times the source column's entry l
+                    auto apply = [&](int tr, R l) {
+                        xw[tr * T + t] = fma(-m0, l, xw[tr * T + t]);
+                        if (two) xw1[tr * T + t] = fma(-m1, l, xw1[tr * T + t]);
+                        if (tr == dr) ysl[t] = fma(-l, ykg, ysl[t]);
+                        else if (two && tr == dr + 1) ysl1[t] = fma(-l, ykg, ysl1[t]);
+                    };
+#pragma unroll
+                    for (int e = 0; e < L_ROWS; e++)
+                        if (rv[g][e] >= 0) apply(rv[g][e], lv[g][e]);
+                    if constexpr (WIDE) {
+                        // rows past the column's end read the following entries and the
+                        // padded target table, and are discarded
+                        for (int r = s + L_ROWS * SL; r < lcnt; r += 4 * SL) {
+                            R lx[4];
+                            int tx[4];
+#pragma unroll
+                            for (int x = 0; x < 4; x++) {
+                                lx[x] = LU[(size_t)(up.lbeg + r + x * SL) * T + t];
+                                tx[x] = P.rel[up.roff + r + x * SL];
+                            }
+#pragma unroll
+                            for (int x = 0; x < 4; x++)
+                                if (r + x * SL < lcnt) apply(tx[x], lx[x]);
+                        }
+                    } else {
+                        for (int r = s + L_ROWS * SL; r < lcnt; r += 2 * SL) {
+                            const bool h2 = r + SL < lcnt;
+                            const R l = LU[(size_t)(up.lbeg + r) * T + t];
+                            const int tr = P.rel[up.roff + r];
+                            const R l2 = h2 ? LU[(size_t)(up.lbeg + r + SL) * T + t] : (R)0;
+                            const int tr2 = h2 ? P.rel[up.roff + r + SL] : 0;
+                            apply(tr, l);
+                            if (h2) apply(tr2, l2);
+                        }
+                    }
+                    wave_sync();
+                }
+            }
+            ub += gcnt;
+        }
+        wave_sync();
+        // a pivot that is not finite, not above 1e-300, or tiny against its column of A
+        // (1e-14 of the largest magnitude in FP64, 1e-7 in FP32) fails the instance
+        constexpr R kRelPivot = sizeof(R) == 8 ? (R)1e-14 : (R)1e-7;
+        const R d = xw[dr * T + t];
+        if (s == 0 && valid && !(fabs((double)d) > 1e-300 && isfinite((double)d) && fabs(d) >= kRelPivot * cmx[t]))
+            s_piv[t] = 1;
+        const R rd = (R)1 / d;          // one reciprocal per pivot, not a division per row
+        for (int e = dr + 1 + s; e < cnt; e += SL) xw[e * T + t] = xw[e * T + t] * rd;
+        wave_sync();
+        if (two) {
+            // the pair's second column receives the update of the first (its last source)
+            const R m = xw1[dr * T + t];
+            for (int e = dr + 1 + s; e < cnt; e += SL) xw1[e * T + t] = fma(-m, xw[e * T + t], xw1[e * T + t]);
+            wave_sync();
+            if (s == 0) ysl1[t] = fma(-xw[(dr + 1) * T + t], ysl[t], ysl1[t]);
+            const R d1 = xw1[(dr + 1) * T + t];
+            if (s == 0 && valid &&
+                !(fabs((double)d1) > 1e-300 && isfinite((double)d1) && fabs(d1) >= kRelPivot * cmx1[t]))
+                s_piv[t] = 1;
+            const R rd1 = (R)1 / d1;
+            for (int e = dr + 2 + s; e < cnt; e += SL) xw1[e * T + t] = xw1[e * T + t] * rd1;
+            wave_sync();
+        }
+        wait_loads_returned();
+        for (int e = s; e < cnt; e += SL) {
+            LU[(size_t)(cs + e) * T + t] = xw[e * T + t];
+            if (two) LU[(size_t)(cs + cnt + e) * T + t] = xw1[e * T + t];
+        }
+        if (s == 0) {
+            Yv[j * T + t] = ysl[t];
+            if (two) Yv[(j + 1) * T + t] = ysl1[t];
+        }
+        wave_sync();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __hip_atomic_store(&done[j], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (two) __hip_atomic_store(&done[j + 1], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (pd.lrank >= 0) __hip_atomic_store(&ldone[pd.lrank], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        note_progress(s_prog, wave, nprog);
+    }
+}
+
+// ---- backward substitution and, with upd_v, the voltage update of active instances
+// (Sec. 4.3.3, in the same dataflow style); the factors are in LU, y in Yv.
+// WIDE: the per-phase kernel prefetches each row's next entry chunk (indices, then U
+// values) ahead of its wait; the fused kernel is at its register limit.
+template <typename R, int T, int NW, bool WIDE>
+__device__ __forceinline__ void bs_phase(TileCtx<R> &cx, const bool upd_v)
+{
+    constexpr int SL = 64 / T;
+    const KArgs &a = cx.a;
+    const DevPlan &P = a.p;
+    const int tid = cx.tid, wave = cx.wave, lane = cx.lane, t = cx.t, s = cx.s;
+    (void)tid;
+    const int N = P.N;
+    R *const LU = cx.LU;
+    R *const Yv = cx.Yv;
+    double *const Vm = cx.Vm, *const Va = cx.Va;
+    unsigned char *const done = cx.done;
+    int *const err = cx.err, *const s_prog = cx.s_prog;
+    const int *const s_active = cx.s_active, *const s_reset = cx.s_reset;
+    int &nprog = cx.nprog;
+    R *const zlds = cx.zlds;
+    const int zb = cx.zb;
+    (void)err; (void)N;
+    const BsPanel *bsd = P.bs_desc + (size_t)a.sched * P.n_panels;
+    auto bs_chunk = [&](int c) -> int {
+        const int qq = wave + NW * (8 * c + (lane >> 3));
+        return reinterpret_cast<const int *>(bsd)[(size_t)qq * 8 + (lane & 7)];   // padded table
+    };
+    int bch0 = bs_chunk(0), bch1 = bs_chunk(1);
+    // FP32-LU: the first entry chunk of the wavefront's next row is loaded while the
+    // current row runs, so a row starts with its poll (measured 1-3% faster; in the FP64
+    // kernels the extra registers cost more than the round trip saved)
+    constexpr bool kBsAhead = sizeof(R) == 4 && !WIDE;
+    int nc_all = 0, npq_all = 0;
+    if constexpr (kBsAhead) {
+        const int q0f = __builtin_amdgcn_readlane(bch0, 4);
+        nc_all = P.bs_col[q0f + s];       // padded tables
+        npq_all = P.bs_pos[q0f + s];
+    }
+    wait_loads_returned();
+    for (int q = wave, qi = 0; q < P.n_panels; q += NW, qi++) {
+        const int kq = qi & 7;
+        BsPanel pd;
+        {
+            int *w = reinterpret_cast<int *>(&pd);
+#pragma unroll
+            for (int f = 0; f < 8; f++) w[f] = __builtin_amdgcn_readlane(bch0, kq * 8 + f);
+        }
+        int c0_all = 0, pq0_all = 0;
+        if constexpr (kBsAhead) {
+            c0_all = nc_all;
+            pq0_all = npq_all;
+            const int q0n = kq < 7 ? __builtin_amdgcn_readlane(bch0, (kq + 1) * 8 + 4)
+                                   : __builtin_amdgcn_readlane(bch1, 4);
+            nc_all = P.bs_col[q0n + s];
+            npq_all = P.bs_pos[q0n + s];
+        }
+        if (kq == 7) {
+            bch0 = bch1;
+            bch1 = bs_chunk((qi >> 3) + 2);
+        }
+        const int j = pd.j2 & ((1 << 30) - 1);
+        const bool two = (pd.j2 >> 30) & 1;
+        const int cs = pd.cs, dr = pd.dr, cs1 = pd.cs1;
+        const int pu = pd.pu;
+        const int bus = pu >> 1;
+        // operands that no other row changes, loaded before the wait so that their
+        // latency overlaps it: right-hand sides, diagonal (and for a pair the coupling
+        // U(j, j+1)), and the voltages to update
+        const R y0 = Yv[j * T + t];
+        const R d0 = LU[(size_t)(cs + dr) * T + t];
+        const R y1 = two ? Yv[(j + 1) * T + t] : (R)0;
+        const R d1 = two ? LU[(size_t)(cs1 + dr + 1) * T + t] : (R)1;
+        const R u01 = two ? LU[(size_t)(cs1 + dr) * T + t] : (R)0;
+        const double vm_old = Vm[bus * T + t], va_old = Va[bus * T + t];
+        R acc0 = 0, acc1 = 0;
+        const int q0 = pd.q0, q1 = pd.q1;
+        // SL entries of the row at a time: each lane loads its entry's column and
+        // position, the wavefront waits until all those rows are published, then the
+        // operands are loaded.  The FP64 kernels keep the plain loop below: the same
+        // body written once as a lambda for both branches compiles, in FP64, to a
+        // measurably slower register allocation (7% on the 1350-bus workload).
+        if constexpr (kBsAhead) {
+            auto chunk = [&](int qb, int c_all, int pq_all) {
+                const int q = qb + s;
+                const bool in = q < q1;
+                const int c = in ? c_all : -1;
+                const int pq = in ? pq_all : 1;
+                unsigned spins = 0;
+                int seen = -1;
+                for (;;) {
+                    const bool ok = c < 0 || __hip_atomic_load(&done[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (__all(ok) || wait_tick<NW>(spins, seen, s_prog, err)) break;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const R z = Yv[(in ? c : j) * T + t];
+                const R l1 = LU[(size_t)pq * T + t];
+                const R l0 = LU[(size_t)(pq - 1) * T + t];
+                if (in) {
+                    if (two) {
+                        acc1 = fma(l1, z, acc1);
+                        acc0 = fma(l0, z, acc0);
+                    } else {
+                        acc0 = fma(l1, z, acc0);
+                    }
+                }
+            };
+            if (q0 < q1) chunk(q0, c0_all, pq0_all);
+            for (int qb = q0 + SL; qb < q1; qb += SL) chunk(qb, P.bs_col[qb + s], P.bs_pos[qb + s]);
+        } else if constexpr (WIDE) {
+            // U values and column indices do not depend on other rows: the indices of the
+            // next two chunks and the U values of the next are in flight while the current
+            // chunk waits for its rows (padded tables; positions clamped to 1); z of the
+            // positions held in LDS is read from there
+            int ca = P.bs_col[q0 + s], pa = max(P.bs_pos[q0 + s], 1);
+            R ua1 = LU[(size_t)pa * T + t], ua0 = LU[(size_t)(pa - 1) * T + t];
+            int cb = P.bs_col[q0 + SL + s], pb = P.bs_pos[q0 + SL + s];
+            for (int qb = q0; qb < q1; qb += SL) {
+                const bool in = qb + s < q1;
+                const int c = in ? ca : -1;
+                const R l1 = ua1, l0 = ua0;
+                ca = cb;
+                pa = max(pb, 1);
+                ua1 = LU[(size_t)pa * T + t];
+                ua0 = LU[(size_t)(pa - 1) * T + t];
+                cb = P.bs_col[qb + 2 * SL + s];
+                pb = P.bs_pos[qb + 2 * SL + s];
+                unsigned spins = 0;
+                int seen = -1;
+                for (;;) {
+                    const bool ok = c < 0 || __hip_atomic_load(&done[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (__all(ok) || wait_tick<NW>(spins, seen, s_prog, err)) break;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const int cz = in ? c : j;
+                const R z = cz >= zb ? zlds[(cz - zb) * T + t] : Yv[cz * T + t];
+                if (in) {
+                    if (two) {
+                        acc1 = fma(l1, z, acc1);
+                        acc0 = fma(l0, z, acc0);
+                    } else {
+                        acc0 = fma(l1, z, acc0);
+                    }
+                }
+            }
+        } else {
+            for (int qb = q0; qb < q1; qb += SL) {
+                const int q = qb + s;
+                const bool in = q < q1;
+                const int c_all = P.bs_col[q], pq_all = P.bs_pos[q];   // padded tables
+                const int c = in ? c_all : -1;
+                const int pq = in ? pq_all : 1;
+                unsigned spins = 0;
+                int seen = -1;
+                for (;;) {
+                    const bool ok = c < 0 || __hip_atomic_load(&done[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (__all(ok) || wait_tick<NW>(spins, seen, s_prog, err)) break;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const R z = Yv[(in ? c : j) * T + t];
+                const R l1 = LU[(size_t)pq * T + t];
+                const R l0 = LU[(size_t)(pq - 1) * T + t];
+                if (in) {
+                    if (two) {
+                        acc1 = fma(l1, z, acc1);
+                        acc0 = fma(l0, z, acc0);
+                    } else {
+                        acc0 = fma(l1, z, acc0);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int off = T; off < 64; off <<= 1) {
+            acc0 += __shfl_xor(acc0, off);
+            acc1 += __shfl_xor(acc1, off);
+        }
+        wait_loads_returned();
+        if constexpr (WIDE) {
+            R z0 = 0, zl = 0;
+            if (s == 0) {
+                if (two) {
+                    zl = (y1 - acc1) / d1;
+                    acc0 = fma(u01, zl, acc0);
+                }
+                z0 = (y0 - acc0) / d0;
+                if (j >= zb) zlds[(j - zb) * T + t] = z0;
+                if (two && j + 1 >= zb) zlds[(j + 1 - zb) * T + t] = zl;
+            }
+            // a row held in LDS is read only from there, so it publishes before its global
+            // stores; the others publish after them (a pair straddling zb counts as the
+            // latter: its first row is read from global memory)
+            const bool lds_only = j >= zb;
+            auto store_z = [&]() {
+                if (s == 0) {
+                    if (two) Yv[(j + 1) * T + t] = zl;
+                    Yv[j * T + t] = z0;
+                    if (upd_v && s_active[t] && !s_reset[t]) {
+                        if (two) {
+                            Va[bus * T + t] = va_old - (double)z0;
+                            Vm[bus * T + t] = vm_old - (double)zl;
+                        } else if (pu & 1) {
+                            Vm[bus * T + t] = vm_old - (double)z0;
+                        } else {
+                            Va[bus * T + t] = va_old - (double)z0;
+                        }
+                    }
+                }
+            };
+            if (!lds_only) store_z();
+            wave_sync();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __hip_atomic_store(&done[j], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (two) __hip_atomic_store(&done[j + 1], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (lds_only) store_z();
+        } else {
+            if (s == 0) {
+                R zl = 0;
+                if (two) {
+                    zl = (y1 - acc1) / d1;
+                    Yv[(j + 1) * T + t] = zl;
+                    acc0 = fma(u01, zl, acc0);
+                }
+                const R z0 = (y0 - acc0) / d0;
+                Yv[j * T + t] = z0;
+                if (upd_v && s_active[t] && !s_reset[t]) {
+                    if (two) {
+                        Va[bus * T + t] = va_old - (double)z0;
+                        Vm[bus * T + t] = vm_old - (double)zl;
+                    } else if (pu & 1) {
+                        Vm[bus * T + t] = vm_old - (double)z0;
+                    } else {
+                        Va[bus * T + t] = va_old - (double)z0;
+                    }
+                }
+            }
+            wave_sync();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __hip_atomic_store(&done[j], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (two) __hip_atomic_store(&done[j + 1], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        note_progress(s_prog, wave, nprog);
+    }
+}
+
 // The whole Newton loop of one tile (T instances) by one workgroup.  Called by the
 // one-tile-per-workgroup kernel and by the persistent multi-pattern queue kernel.
 template <typename R, int T, int NW>
@@ -187,7 +782,6 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     __shared__ double s_prevf[T];
     __shared__ double s_normf[T];
     __shared__ int s_any, s_err;
-    __shared__ int s_lgen[kMaxLong];    // publications seen by each long working-column slot
     __shared__ int s_prog[NW];          // publications made by each wavefront (progress bound)
 
     const DevPlan &P = a.p;
@@ -212,9 +806,9 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     double *Vm = vec, *Va = vec + nT, *Ps = vec + 2 * nT, *Qs = vec + 3 * nT;
     double2 *Vc = reinterpret_cast<double2 *>(vec + 4 * nT);     // V = |V| e^{j angle}
 
-    // LDS: per wavefront a short working-column pair (slot_rows rows each), n_long shared
-    // long pairs (max_col rows each), per wavefront two right-hand-side slots, then one
-    // publication byte per column
+    // LDS: per wavefront a short working-column pair (slot_rows rows each), the long panels'
+    // ring (n_long * 2 * max_col rows), per wavefront two right-hand-side slots and two
+    // column maxima, then one publication byte per column and one per long panel
     R *const short_base = reinterpret_cast<R *>(smem_raw);
     R *const long_base = short_base + (size_t)NW * 2 * P.slot_rows * T;
     R *ysl = long_base + (size_t)a.n_long * 2 * P.max_col * T + (size_t)wave * 2 * T;
@@ -225,8 +819,11 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     R *cmx1 = cmx + T;
     unsigned char *done = reinterpret_cast<unsigned char *>(
         long_base + (size_t)a.n_long * 2 * P.max_col * T + (size_t)NW * 4 * T);
+    unsigned char *ldone = done + N;
     int *err = &s_err;
     int nprog = 0;                      // this wavefront's publications so far
+    TileCtx<R> cx{a, tid, wave, lane, t, s, valid, LU, Yv, Vm, Va, short_base, long_base, ysl, ysl1, cmx, cmx1,
+                  done, ldone, err, s_prog, s_piv, s_active, s_reset, nprog, nullptr, N};
 
     // ---- boundary layout [B][n][2] -> tile layout [n][T]
     for (int i = slot; i < n; i += SLOTS) {
@@ -386,267 +983,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         }
 
         // ============================ LU: Jacobian -> refactorization -> forward substitution
-        for (int w = tid; w < N; w += NT)
-            __hip_atomic_store(&done[w], (unsigned char)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (tid < kMaxLong) __hip_atomic_store(&s_lgen[tid], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __syncthreads();
-        // Panels (one column, or the angle/|V| pair of a PQ bus sharing one row list) in
-        // level order, round-robin over the wavefronts.  The order is topological, so the
-        // earliest unfinished panel always has every source published and some wavefront
-        // always makes progress; level order keeps independent panels side by side.
-        // The loads of a panel's Jacobian values and right-hand sides do not depend on any
-        // other panel (only the panel itself rewrites its columns and rows), so they are
-        // software-pipelined: while a wavefront works on one panel, the loads of its next
-        // panel are in flight.  A_ROWS rows per lane travel this way; longer panels load
-        // their remaining rows when they start.
-        //
-        // Metadata travels in vector registers instead of scalar loads (a scalar load is
-        // counted together with LDS operations, so every LDS wait would also wait for it):
-        // one load brings the descriptors of the wavefront's next 8 panels (lane l holds
-        // word l % 8 of descriptor l / 8) and one load 16 update records of a panel (lane l
-        // holds word l % 4 of record l / 4); fields are read with readlane.  A panel's first
-        // 16 records arrive with its prefetch; a panel with more loads each further chunk
-        // one chunk ahead of its use, so no update group waits for its own records.
-        const LuPanel *lud = P.lu_desc + (size_t)a.sched * P.n_panels;
-        auto desc_chunk = [&](int c) -> int {
-            const int qq = wave + NW * (8 * c + (lane >> 3));
-            return reinterpret_cast<const int *>(lud)[(size_t)qq * 8 + (lane & 7)];   // padded table
-        };
-        auto desc_from = [&](int chunk, int k) -> LuPanel {
-            LuPanel d;
-            int *w = reinterpret_cast<int *>(&d);
-#pragma unroll
-            for (int f = 0; f < 8; f++) w[f] = __builtin_amdgcn_readlane(chunk, k * 8 + f);
-            return d;
-        };
-        // records [ua, ua + 16); only those below the panel's end are read back (the table
-        // is padded by one chunk)
-        auto upd_chunk_at = [&](int ua) -> int { return reinterpret_cast<const int *>(P.upd)[(size_t)ua * 4 + lane]; };
-        auto upd_chunk = [&](const LuPanel &d) -> int { return upd_chunk_at(d.u0); };
-        R pa0[A_ROWS], pa1[A_ROWS], py0 = 0, py1 = 0;
-        unsigned char pf[A_ROWS];
-        int pupd = 0;
-        auto prefetch = [&](const LuPanel &d) {
-            pupd = upd_chunk(d);
-            const int jn = d.j2 & ((1 << 30) - 1);
-            const bool tw = (d.j2 >> 30) & 1;
-#pragma unroll
-            for (int r = 0; r < A_ROWS; r++) {
-                const int e = min(s + r * SL, d.cnt - 1);      // rows past the end re-read the last
-                pf[r] = P.isj[d.cs + e];
-                pa0[r] = LU[(size_t)(d.cs + e) * T + t];
-                pa1[r] = LU[(size_t)(d.cs + (tw ? d.cnt : 0) + e) * T + t];
-            }
-            py0 = Yv[jn * T + t];
-            py1 = Yv[(jn + (tw ? 1 : 0)) * T + t];
-        };
-        int dch0 = desc_chunk(0), dch1 = desc_chunk(1);
-        LuPanel pdc = desc_from(dch0, 0);         // the current panel's descriptor, kept in
-        if (wave < P.n_panels) prefetch(pdc);     // scalar registers across iterations
-        wait_loads_returned();
-        for (int q = wave, qi = 0; q < P.n_panels; q += NW, qi++) {
-            const int kq = qi & 7;
-            const LuPanel pd = pdc;
-            const int ucur = pupd;
-            const int j = pd.j2 & ((1 << 30) - 1);
-            const bool two = (pd.j2 >> 30) & 1;
-            const int cs = pd.cs, cnt = pd.cnt, dr = pd.dr;
-            const bool more = q + NW < P.n_panels;
-            const LuPanel pdn = kq < 7 ? desc_from(dch0, kq + 1) : desc_from(dch1, 0);
-            if (kq == 7) {
-                dch0 = dch1;
-                dch1 = desc_chunk((qi >> 3) + 2);
-            }
-            R *xw, *xw1;
-            // a long panel of rank r takes slot r mod n_long once the slot has seen r / n_long
-            // publications, i.e. once the long panel of rank r - n_long (earlier in the same
-            // topological order) has published
-            // (the quotient by a multiply-high with the rounded-up reciprocal, exact for ranks
-            // below 2^29; an integer division would be emulated on vector registers; with one
-            // slot the reciprocal 2^32 does not fit and the rank is the quotient)
-            const int lgen = pd.lrank < 0 ? 0
-                             : a.n_long == 1 ? pd.lrank : (int)__umulhi((unsigned)pd.lrank, a.n_long_inv);
-            const int lslot = pd.lrank < 0 ? -1 : pd.lrank - lgen * a.n_long;
-            if (lslot < 0) {
-                xw = short_base + (size_t)wave * 2 * P.slot_rows * T;
-                xw1 = xw + (size_t)P.slot_rows * T;
-            } else {
-                if (lgen > 0) wait_count<NW>(&s_lgen[lslot], lgen, s_prog, err);
-                xw = long_base + (size_t)lslot * 2 * P.max_col * T;
-                xw1 = xw + (size_t)P.max_col * T;
-            }
-            // the panel's Jacobian values (written by the mismatch pass; fill positions read
-            // as zero; both columns of a pair share the row list and the fill pattern) and
-            // right-hand sides
-            {
-                R cm0 = 0, cm1 = 0;
-#pragma unroll
-                for (int r = 0; r < A_ROWS; r++) {
-                    const int e = s + r * SL;
-                    if (e < cnt) {
-                        const R a0 = pf[r] ? pa0[r] : (R)0, a1 = pf[r] ? pa1[r] : (R)0;
-                        xw[e * T + t] = a0;
-                        if (two) xw1[e * T + t] = a1;
-                        cm0 = fmax(cm0, fabs(a0));
-                        cm1 = fmax(cm1, fabs(a1));
-                    }
-                }
-                if (s == 0) {
-                    ysl[t] = py0;
-                    if (two) ysl1[t] = py1;
-                }
-                for (int e = s + A_ROWS * SL; e < cnt; e += SL) {
-                    const bool fe = P.isj[cs + e];
-                    const R v0 = LU[(size_t)(cs + e) * T + t];
-                    const R v1 = two ? LU[(size_t)(cs + cnt + e) * T + t] : (R)0;
-                    const R a0 = fe ? v0 : (R)0, a1 = fe ? v1 : (R)0;
-                    xw[e * T + t] = a0;
-                    if (two) xw1[e * T + t] = a1;
-                    cm0 = fmax(cm0, fabs(a0));
-                    cm1 = fmax(cm1, fabs(a1));
-                }
-                // the column maxima over the instance's sub-lanes, kept in LDS until the pivots
-#pragma unroll
-                for (int off = T; off < 64; off <<= 1) {
-                    cm0 = fmax(cm0, __shfl_xor(cm0, off));
-                    cm1 = fmax(cm1, __shfl_xor(cm1, off));
-                }
-                if (s == 0) {
-                    cmx[t] = cm0;
-                    cmx1[t] = cm1;
-                }
-            }
-            if (more) prefetch(pdn);
-            pdc = pdn;
-            // Updates in ascending source order.  After waiting for the first pending source,
-            // the run of following updates whose sources are already published (up to
-            // UPD_GROUP, within one chunk of records) has its operand loads issued together
-            // (L_ROWS rows of each source column per lane), then the updates are applied one
-            // after another in LDS (the order of the arithmetic is unchanged).  Rows beyond
-            // L_ROWS per lane (the long source columns of the dense tail) are loaded two at a
-            // time.
-            const int u0 = pd.u0, u1 = pd.u1;
-            int ubase = u0, uc0 = ucur, uc1 = 0;
-            if (u1 - u0 > 16) uc1 = upd_chunk_at(u0 + 16);
-            auto upd_rec = [&](int u) -> Update {
-                const int r = u - ubase;
-                Update x;
-                x.krel_lcnt = __builtin_amdgcn_readlane(uc0, 4 * r);
-                x.lbeg = __builtin_amdgcn_readlane(uc0, 4 * r + 1);
-                x.roff = __builtin_amdgcn_readlane(uc0, 4 * r + 2);
-                x.k = __builtin_amdgcn_readlane(uc0, 4 * r + 3);
-                return x;
-            };
-            for (int ub = u0; ub < u1;) {
-                if (ub - ubase >= 16) {
-                    ubase += 16;
-                    uc0 = uc1;
-                    if (u1 - ubase > 16) uc1 = upd_chunk_at(ubase + 16);
-                }
-                Update ups[UPD_GROUP];
-                ups[0] = upd_rec(ub);
-                wait_published<NW>(done, ups[0].k, s_prog, err);
-                int gcnt = 1;
-#pragma unroll
-                for (int g = 1; g < UPD_GROUP; g++) {
-                    if (gcnt == g && ub + g < u1 && ub + g - ubase < 16) {
-                        ups[g] = upd_rec(ub + g);
-                        const int f = __builtin_amdgcn_readfirstlane((int)__hip_atomic_load(
-                            &done[ups[g].k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-                        if (f) gcnt = g + 1;
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                R lv[UPD_GROUP][L_ROWS], yk[UPD_GROUP];
-                int rv[UPD_GROUP][L_ROWS];
-#pragma unroll
-                for (int g = 0; g < UPD_GROUP; g++) {
-                    yk[g] = 0;
-#pragma unroll
-                    for (int e = 0; e < L_ROWS; e++) { lv[g][e] = 0; rv[g][e] = -1; }
-                    if (g < gcnt) {
-                        const int lcnt = ups[g].krel_lcnt >> 16;
-#pragma unroll
-                        for (int e = 0; e < L_ROWS; e++)
-                            if (s + e * SL < lcnt) {
-                                lv[g][e] = LU[(size_t)(ups[g].lbeg + s + e * SL) * T + t];
-                                rv[g][e] = P.rel[ups[g].roff + s + e * SL];
-                            }
-                        yk[g] = Yv[ups[g].k * T + t];
-                    }
-                }
-                wave_sync();
-#pragma unroll
-                for (int g = 0; g < UPD_GROUP; g++) {
-                    if (g < gcnt) {
-                        const Update up = ups[g];
-                        const int krel = up.krel_lcnt & 0xffff, lcnt = up.krel_lcnt >> 16;
-                        const R m0 = xw[krel * T + t];
-                        const R m1 = two ? xw1[krel * T + t] : (R)0;
-                        const R ykg = yk[g];
-                        // row tr of the panel's columns (and its right-hand side) minus the
-                        // multipliers times the source column's entry l
-                        auto apply = [&](int tr, R l) {
-                            xw[tr * T + t] = fma(-m0, l, xw[tr * T + t]);
-                            if (two) xw1[tr * T + t] = fma(-m1, l, xw1[tr * T + t]);
-                            if (tr == dr) ysl[t] = fma(-l, ykg, ysl[t]);
-                            else if (two && tr == dr + 1) ysl1[t] = fma(-l, ykg, ysl1[t]);
-                        };
-#pragma unroll
-                        for (int e = 0; e < L_ROWS; e++)
-                            if (rv[g][e] >= 0) apply(rv[g][e], lv[g][e]);
-                        for (int r = s + L_ROWS * SL; r < lcnt; r += 2 * SL) {
-                            const bool h2 = r + SL < lcnt;
-                            const R l = LU[(size_t)(up.lbeg + r) * T + t];
-                            const int tr = P.rel[up.roff + r];
-                            const R l2 = h2 ? LU[(size_t)(up.lbeg + r + SL) * T + t] : (R)0;
-                            const int tr2 = h2 ? P.rel[up.roff + r + SL] : 0;
-                            apply(tr, l);
-                            if (h2) apply(tr2, l2);
-                        }
-                        wave_sync();
-                    }
-                }
-                ub += gcnt;
-            }
-            wave_sync();
-            // a pivot that is not finite, not above 1e-300, or tiny against its column of A
-            // (1e-14 of the largest magnitude in FP64, 1e-7 in FP32) fails the instance
-            constexpr R kRelPivot = sizeof(R) == 8 ? (R)1e-14 : (R)1e-7;
-            const R d = xw[dr * T + t];
-            if (s == 0 && valid && !(fabs((double)d) > 1e-300 && isfinite((double)d) && fabs(d) >= kRelPivot * cmx[t]))
-                s_piv[t] = 1;
-            for (int e = dr + 1 + s; e < cnt; e += SL) xw[e * T + t] = xw[e * T + t] / d;
-            wave_sync();
-            if (two) {
-                // the pair's second column receives the update of the first (its last source)
-                const R m = xw1[dr * T + t];
-                for (int e = dr + 1 + s; e < cnt; e += SL) xw1[e * T + t] = fma(-m, xw[e * T + t], xw1[e * T + t]);
-                wave_sync();
-                if (s == 0) ysl1[t] = fma(-xw[(dr + 1) * T + t], ysl[t], ysl1[t]);
-                const R d1 = xw1[(dr + 1) * T + t];
-                if (s == 0 && valid &&
-                    !(fabs((double)d1) > 1e-300 && isfinite((double)d1) && fabs(d1) >= kRelPivot * cmx1[t]))
-                    s_piv[t] = 1;
-                for (int e = dr + 2 + s; e < cnt; e += SL) xw1[e * T + t] = xw1[e * T + t] / d1;
-                wave_sync();
-            }
-            wait_loads_returned();
-            for (int e = s; e < cnt; e += SL) {
-                LU[(size_t)(cs + e) * T + t] = xw[e * T + t];
-                if (two) LU[(size_t)(cs + cnt + e) * T + t] = xw1[e * T + t];
-            }
-            if (s == 0) {
-                Yv[j * T + t] = ysl[t];
-                if (two) Yv[(j + 1) * T + t] = ysl1[t];
-            }
-            wave_sync();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __hip_atomic_store(&done[j], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (two) __hip_atomic_store(&done[j + 1], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (lslot >= 0) __hip_atomic_store(&s_lgen[lslot], lgen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            note_progress(s_prog, wave, nprog);
-        }
+        lu_phase<R, T, NW, false>(cx);
         __syncthreads();
         if (tid < T && s_piv[t] && s_active[t] && !s_reset[t] && a.mode == MODE_SOLVE) {
             if (a.v_fb && !s_retry[t]) { s_retry[t] = 1; s_reset[t] = 1; s_base[t] = s_nupd[t]; }
@@ -666,151 +1003,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         // Panels in back-substitution level order.  For a pair (j, j+1) the rows share their
         // column set i > j+1, and U(j, i), U(j+1, i) sit next to each other in column i.
         const bool upd_v = (a.mode == MODE_SOLVE);
-        const BsPanel *bsd = P.bs_desc + (size_t)a.sched * P.n_panels;
-        auto bs_chunk = [&](int c) -> int {
-            const int qq = wave + NW * (8 * c + (lane >> 3));
-            return reinterpret_cast<const int *>(bsd)[(size_t)qq * 8 + (lane & 7)];   // padded table
-        };
-        int bch0 = bs_chunk(0), bch1 = bs_chunk(1);
-        // FP32-LU: the first entry chunk of the wavefront's next row is loaded while the
-        // current row runs, so a row starts with its poll (measured 1-3% faster; in the FP64
-        // kernels the extra registers cost more than the round trip saved)
-        constexpr bool kBsAhead = sizeof(R) == 4;
-        int nc_all = 0, npq_all = 0;
-        if constexpr (kBsAhead) {
-            const int q0f = __builtin_amdgcn_readlane(bch0, 4);
-            nc_all = P.bs_col[q0f + s];       // padded tables
-            npq_all = P.bs_pos[q0f + s];
-        }
-        wait_loads_returned();
-        for (int q = wave, qi = 0; q < P.n_panels; q += NW, qi++) {
-            const int kq = qi & 7;
-            BsPanel pd;
-            {
-                int *w = reinterpret_cast<int *>(&pd);
-#pragma unroll
-                for (int f = 0; f < 8; f++) w[f] = __builtin_amdgcn_readlane(bch0, kq * 8 + f);
-            }
-            int c0_all = 0, pq0_all = 0;
-            if constexpr (kBsAhead) {
-                c0_all = nc_all;
-                pq0_all = npq_all;
-                const int q0n = kq < 7 ? __builtin_amdgcn_readlane(bch0, (kq + 1) * 8 + 4)
-                                       : __builtin_amdgcn_readlane(bch1, 4);
-                nc_all = P.bs_col[q0n + s];
-                npq_all = P.bs_pos[q0n + s];
-            }
-            if (kq == 7) {
-                bch0 = bch1;
-                bch1 = bs_chunk((qi >> 3) + 2);
-            }
-            const int j = pd.j2 & ((1 << 30) - 1);
-            const bool two = (pd.j2 >> 30) & 1;
-            const int cs = pd.cs, dr = pd.dr, cs1 = pd.cs1;
-            const int pu = pd.pu;
-            const int bus = pu >> 1;
-            // operands that no other row changes, loaded before the wait so that their
-            // latency overlaps it: right-hand sides, diagonal (and for a pair the coupling
-            // U(j, j+1)), and the voltages to update
-            const R y0 = Yv[j * T + t];
-            const R d0 = LU[(size_t)(cs + dr) * T + t];
-            const R y1 = two ? Yv[(j + 1) * T + t] : (R)0;
-            const R d1 = two ? LU[(size_t)(cs1 + dr + 1) * T + t] : (R)1;
-            const R u01 = two ? LU[(size_t)(cs1 + dr) * T + t] : (R)0;
-            const double vm_old = Vm[bus * T + t], va_old = Va[bus * T + t];
-            R acc0 = 0, acc1 = 0;
-            const int q0 = pd.q0, q1 = pd.q1;
-            // SL entries of the row at a time: each lane loads its entry's column and
-            // position, the wavefront waits until all those rows are published, then the
-            // operands are loaded.  The FP64 kernels keep the plain loop below: the same
-            // body written once as a lambda for both branches compiles, in FP64, to a
-            // measurably slower register allocation (7% on the 1350-bus workload).
-            if constexpr (kBsAhead) {
-                auto chunk = [&](int qb, int c_all, int pq_all) {
-                    const int q = qb + s;
-                    const bool in = q < q1;
-                    const int c = in ? c_all : -1;
-                    const int pq = in ? pq_all : 1;
-                    unsigned spins = 0;
-                    int seen = -1;
-                    for (;;) {
-                        const bool ok = c < 0 || __hip_atomic_load(&done[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        if (__all(ok) || wait_tick<NW>(spins, seen, s_prog, err)) break;
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                    const R z = Yv[(in ? c : j) * T + t];
-                    const R l1 = LU[(size_t)pq * T + t];
-                    const R l0 = LU[(size_t)(pq - 1) * T + t];
-                    if (in) {
-                        if (two) {
-                            acc1 = fma(l1, z, acc1);
-                            acc0 = fma(l0, z, acc0);
-                        } else {
-                            acc0 = fma(l1, z, acc0);
-                        }
-                    }
-                };
-                if (q0 < q1) chunk(q0, c0_all, pq0_all);
-                for (int qb = q0 + SL; qb < q1; qb += SL) chunk(qb, P.bs_col[qb + s], P.bs_pos[qb + s]);
-            } else {
-                for (int qb = q0; qb < q1; qb += SL) {
-                    const int q = qb + s;
-                    const bool in = q < q1;
-                    const int c_all = P.bs_col[q], pq_all = P.bs_pos[q];   // padded tables
-                    const int c = in ? c_all : -1;
-                    const int pq = in ? pq_all : 1;
-                    unsigned spins = 0;
-                    int seen = -1;
-                    for (;;) {
-                        const bool ok = c < 0 || __hip_atomic_load(&done[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        if (__all(ok) || wait_tick<NW>(spins, seen, s_prog, err)) break;
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                    const R z = Yv[(in ? c : j) * T + t];
-                    const R l1 = LU[(size_t)pq * T + t];
-                    const R l0 = LU[(size_t)(pq - 1) * T + t];
-                    if (in) {
-                        if (two) {
-                            acc1 = fma(l1, z, acc1);
-                            acc0 = fma(l0, z, acc0);
-                        } else {
-                            acc0 = fma(l1, z, acc0);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int off = T; off < 64; off <<= 1) {
-                acc0 += __shfl_xor(acc0, off);
-                acc1 += __shfl_xor(acc1, off);
-            }
-            wait_loads_returned();
-            if (s == 0) {
-                R zl = 0;
-                if (two) {
-                    zl = (y1 - acc1) / d1;
-                    Yv[(j + 1) * T + t] = zl;
-                    acc0 = fma(u01, zl, acc0);
-                }
-                const R z0 = (y0 - acc0) / d0;
-                Yv[j * T + t] = z0;
-                if (upd_v && s_active[t] && !s_reset[t]) {
-                    if (two) {
-                        Va[bus * T + t] = va_old - (double)z0;
-                        Vm[bus * T + t] = vm_old - (double)zl;
-                    } else if (pu & 1) {
-                        Vm[bus * T + t] = vm_old - (double)z0;
-                    } else {
-                        Va[bus * T + t] = va_old - (double)z0;
-                    }
-                }
-            }
-            wave_sync();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __hip_atomic_store(&done[j], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (two) __hip_atomic_store(&done[j + 1], (unsigned char)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            note_progress(s_prog, wave, nprog);
-        }
+        bs_phase<R, T, NW, false>(cx, upd_v);
         __syncthreads();
         if (a.mode == MODE_STEP) {
             if (valid)
@@ -879,24 +1072,355 @@ __global__ void queue_reset_kernel(int *counters, int n, unsigned long long *t0)
     if (threadIdx.x == 0) *t0 = wall_clock64();
 }
 
+// ------------------------------------------------------------------ per-phase launches
+// The same Newton iterations as nr_tile_body, one launch per phase and iteration, so that
+// each phase runs with its own register budget and launch shape: the mismatch and Jacobian
+// (a3, a4) over every (bus, instance) of the batch at full occupancy, the refactorization
+// (a5, a6 forward) and the back substitution with the voltage update (a6, a7) per tile.
+// The loop stays on the host as a fixed sequence of launches; an instance's state
+// (status, iterations, updates, active) and its tile's flags live in the tile's block of
+// the workspace, and a tile whose instances have all stopped returns at once.
+
+// The per-phase kernels use the refactorization's wider load batches (measured on 2,000
+// scenarios of the 9000-bus grid: FP64 64.7 -> 61.0 ms, FP32-LU 44.1 -> 44.2 ms); the back
+// substitution's prefetch and LDS copy of z are slower there (66.6 / 47.7 ms with them)
+// and stay off.
+template <typename R> constexpr bool kWideLu = true;
+template <typename R> constexpr bool kWideBs = false;
+
+template <int T>
+__device__ __forceinline__ int4 *tile_ctl(const KArgs &a, int tile)
+{
+    return reinterpret_cast<int4 *>(a.ws + (size_t)tile * a.tile_bytes + a.off_ctl);
+}
+
+// boundary layout [B][n][2] -> tile layout; instance states and tile flags initialised
+template <int T>
+__global__ __launch_bounds__(kMBlock) void split_in_kernel(KArgs a)
+{
+    const int tile = blockIdx.x, tid = threadIdx.x, t = tid % T;
+    const int b = tile * T + t;
+    const bool valid = b < a.batch;
+    const int n = a.p.n;
+    double *vec = reinterpret_cast<double *>(a.ws + (size_t)tile * a.tile_bytes + a.off_vec);
+    const size_t nT = (size_t)n * T;
+    for (int i = tid / T; i < n; i += kMBlock / T) {
+        double vm = 1.0, va = 0.0, ps = 0.0, qs = 0.0;
+        if (valid) {
+            const size_t o = ((size_t)b * n + i) * 2;
+            vm = a.v0[o]; va = a.v0[o + 1];
+            ps = a.sbus[o]; qs = a.sbus[o + 1];
+        }
+        vec[i * T + t] = vm; vec[nT + i * T + t] = va;
+        vec[2 * nT + i * T + t] = ps; vec[3 * nT + i * T + t] = qs;
+    }
+    int4 *ctl = tile_ctl<T>(a, tile);
+    if (tid < T) ctl[t] = make_int4(PF_ST_MAXITER, 0, 0, valid ? 1 : 0);
+    if (tid == 0) {
+        int *tf = reinterpret_cast<int *>(ctl + T);
+        tf[0] = tile * T < a.batch ? 1 : 0;
+        tf[1] = 0;
+    }
+}
+
+// rectangular V = |V| e^{j angle} of every bus of the active tiles (one sine/cosine per
+// bus, as in nr_tile_body)
+template <int T>
+__global__ __launch_bounds__(kMBlock) void split_v_kernel(KArgs a, int ntiles)
+{
+    const int tid = threadIdx.x, t = tid % T;
+    const int n = a.p.n, nbb = a.nbb;
+    const size_t nT = (size_t)n * T;
+    const int nitems = ntiles * nbb;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int tile = item / nbb, blk = item - tile * nbb;
+        char *base = a.ws + (size_t)tile * a.tile_bytes;
+        const int4 *ctl = reinterpret_cast<const int4 *>(base + a.off_ctl);
+        if (!reinterpret_cast<const int *>(ctl + T)[0]) continue;
+        const int i = blk * (kMBlock / T) + tid / T;
+        if (i >= n) continue;
+        double *vec = reinterpret_cast<double *>(base + a.off_vec);
+        double2 *Vc = reinterpret_cast<double2 *>(vec + 4 * nT);
+        double sn, cs;
+        const double vm = vec[i * T + t];
+        sincos_angle(vec[nT + i * T + t], &sn, &cs);
+        Vc[i * T + t] = make_double2(vm * cs, vm * sn);
+    }
+}
+
+// mismatch (Eq. 1) and, with build, the Jacobian written into the LU positions (Sec. 3.1.2)
+// for kMBlock / T buses of one tile per work item; each work item leaves the largest |F|
+// (and a non-finite flag) of its buses per instance for the convergence decision
+template <typename R, int T>
+__global__ __launch_bounds__(kMBlock) void split_m_kernel(KArgs a, int ntiles, int build)
+{
+    constexpr int BUSB = kMBlock / T;
+    __shared__ double s_mx[kMBlock];
+    __shared__ int s_bd[kMBlock];
+    const DevPlan &P = a.p;
+    const int tid = threadIdx.x, t = tid % T, ib = tid / T;
+    const int n = P.n, nbb = a.nbb;
+    const size_t nT = (size_t)n * T;
+    const int nitems = ntiles * nbb;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int tile = item / nbb, blk = item - tile * nbb;
+        char *base = a.ws + (size_t)tile * a.tile_bytes;
+        const int4 *ctl = reinterpret_cast<const int4 *>(base + a.off_ctl);
+        if (!reinterpret_cast<const int *>(ctl + T)[0]) continue;      // no instance active
+        R *LU = reinterpret_cast<R *>(base);
+        R *Yv = reinterpret_cast<R *>(base + a.off_y);
+        const double *vec = reinterpret_cast<const double *>(base + a.off_vec);
+        const double *Vm = vec, *Ps = vec + 2 * nT, *Qs = vec + 3 * nT;
+        const double2 *Vc = reinterpret_cast<const double2 *>(vec + 4 * nT);
+        const int b = tile * T + t;
+        const bool valid = b < a.batch;
+        const double2 *yrow = reinterpret_cast<const double2 *>(a.ybus + (valid ? (size_t)b * a.ybus_stride : 0));
+        const int i = blk * BUSB + ib;
+        double mx = 0.0;
+        int bad = 0;
+        if (i < n) {
+            const double2 vv = Vc[i * T + t];
+            double ir = 0.0, ii = 0.0;
+            double2 ydg = make_double2(0.0, 0.0);
+            int qdg = -1;
+            for (int q = P.yrp[i]; q < P.yrp[i + 1]; q++) {
+                const int k = P.yci[q];
+                const double2 y = yrow[q];
+                const double2 v = Vc[k * T + t];
+                const double cr = y.x * v.x - y.y * v.y, ci = y.x * v.y + y.y * v.x;     // Y_ik V_k
+                ir += cr;
+                ii += ci;
+                if (k == i) {
+                    ydg = y;
+                    qdg = q;
+                } else if (build) {
+                    const JPos jp = P.jpos[q];
+                    const double inv = 1.0 / Vm[k * T + t];
+                    const double wr = vv.x * cr + vv.y * ci, wi = vv.y * cr - vv.x * ci;
+                    if (jp.pt >= 0) LU[(size_t)jp.pt * T + t] = (R)wi;
+                    if (jp.pv >= 0) LU[(size_t)jp.pv * T + t] = (R)(wr * inv);
+                    if (jp.qt >= 0) LU[(size_t)jp.qt * T + t] = (R)(-wr);
+                    if (jp.qv >= 0) LU[(size_t)jp.qv * T + t] = (R)(wi * inv);
+                }
+            }
+            const double sr = vv.x * ir + vv.y * ii, si = vv.y * ir - vv.x * ii;       // S_i
+            if (build && qdg >= 0) {
+                const JPos jp = P.jpos[qdg];
+                const double vmi = Vm[i * T + t];
+                const double m2 = vmi * vmi;
+                if (jp.pt >= 0) LU[(size_t)jp.pt * T + t] = (R)(-si - m2 * ydg.y);
+                if (jp.pv >= 0) LU[(size_t)jp.pv * T + t] = (R)(sr / vmi + vmi * ydg.x);
+                if (jp.qt >= 0) LU[(size_t)jp.qt * T + t] = (R)(sr - m2 * ydg.x);
+                if (jp.qv >= 0) LU[(size_t)jp.qv * T + t] = (R)(si / vmi - vmi * ydg.y);
+            }
+            const int pe = P.bus_peq[i], qe = P.bus_qeq[i];
+            if (pe >= 0) {
+                const double f = sr - Ps[i * T + t];
+                Yv[pe * T + t] = (R)f;
+                if (!isfinite(f)) bad = 1; else mx = fmax(mx, fabs(f));
+            }
+            if (qe >= 0) {
+                const double f = si - Qs[i * T + t];
+                Yv[qe * T + t] = (R)f;
+                if (!isfinite(f)) bad = 1; else mx = fmax(mx, fabs(f));
+            }
+        }
+        s_mx[tid] = mx;
+        s_bd[tid] = bad;
+        __syncthreads();
+        if (tid < T) {
+            double m = 0.0;
+            int bd = 0;
+            for (int x = 0; x < BUSB; x++) { m = fmax(m, s_mx[x * T + t]); bd |= s_bd[x * T + t]; }
+            double *pm = reinterpret_cast<double *>(base + a.off_part);
+            int *pb = reinterpret_cast<int *>(pm + (size_t)nbb * T);
+            pm[blk * T + t] = m;
+            pb[blk * T + t] = bd;
+        }
+        __syncthreads();
+    }
+}
+
+// The convergence decision of instance t of a tile from the mismatch kernel's maxima (the
+// same rule as nr_tile_body: non-finite, below tol, or max_iter updates done); called by the
+// tile's first T threads.  Returns whether the instance stays active.
+template <int T>
+__device__ __forceinline__ int split_decide(const KArgs &a, int tile, int t)
+{
+    int4 *ctl = tile_ctl<T>(a, tile);
+    int4 c = ctl[t];
+    if (c.w) {
+        const double *pm = reinterpret_cast<const double *>(a.ws + (size_t)tile * a.tile_bytes + a.off_part);
+        const int *pb = reinterpret_cast<const int *>(pm + (size_t)a.nbb * T);
+        double nf = 0.0;
+        int nb = 0;
+        for (int k = 0; k < a.nbb; k++) { nf = fmax(nf, pm[k * T + t]); nb |= pb[k * T + t]; }
+        int fail = 0;
+        if (nb) fail = PF_ST_NONFINITE;
+        else if (nf < a.tol) { c.x = PF_ST_CONVERGED; c.w = 0; c.y = c.z; }
+        else if (c.z >= a.max_iter) fail = PF_ST_MAXITER;
+        if (fail) { c.x = fail; c.w = 0; c.y = c.z; }
+        ctl[t] = c;
+    }
+    return c.w;
+}
+
+// The tile's LDS view of nr_tile_body for the refactorization (same layout)
+template <typename R, int T, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void split_lu_kernel(KArgs a)
+{
+    extern __shared__ char smem_raw[];
+    __shared__ int s_active[T], s_piv[T], s_reset[T];
+    __shared__ int s_any, s_err;
+    __shared__ int s_prog[NW];
+    const DevPlan &P = a.p;
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, t = lane % T, s = lane / T;
+    const bool valid = tile * T + t < a.batch;
+    int4 *ctl = tile_ctl<T>(a, tile);
+    int *tf = reinterpret_cast<int *>(ctl + T);
+    if (!__builtin_amdgcn_readfirstlane(tf[0])) return;
+    if (tid < T) {
+        s_active[t] = split_decide<T>(a, tile, t);
+        s_piv[t] = 0;
+        s_reset[t] = 0;
+    }
+    if (tid == 0) s_err = 0;
+    if (tid < NW) s_prog[tid] = 0;
+    __syncthreads();
+    if (tid == 0) {
+        int any = 0;
+        for (int q = 0; q < T; q++) any |= s_active[q];
+        s_any = any;
+        tf[0] = any;
+    }
+    __syncthreads();
+    if (!s_any) return;
+    char *base = a.ws + (size_t)tile * a.tile_bytes;
+    double *vec = reinterpret_cast<double *>(base + a.off_vec);
+    const size_t nT = (size_t)P.n * T;
+    R *const short_base = reinterpret_cast<R *>(smem_raw);
+    R *const long_base = short_base + (size_t)NW * 2 * P.slot_rows * T;
+    R *ysl = long_base + (size_t)a.n_long * 2 * P.max_col * T + (size_t)wave * 2 * T;
+    R *cmx = long_base + (size_t)a.n_long * 2 * P.max_col * T + (size_t)NW * 2 * T + (size_t)wave * 2 * T;
+    unsigned char *done = reinterpret_cast<unsigned char *>(
+        long_base + (size_t)a.n_long * 2 * P.max_col * T + (size_t)NW * 4 * T);
+    int nprog = 0;
+    TileCtx<R> cx{a, tid, wave, lane, t, s, valid, reinterpret_cast<R *>(base), reinterpret_cast<R *>(base + a.off_y),
+                  vec, vec + nT, short_base, long_base, ysl, ysl + T, cmx, cmx + T, done, done + P.N, &s_err,
+                  s_prog, s_piv, s_active, s_reset, nprog, nullptr, P.N};
+    lu_phase<R, T, NW, kWideLu<R>>(cx);
+    __syncthreads();
+    if (tid < T && s_piv[t] && s_active[t]) {
+        int4 c = ctl[t];
+        c.x = PF_ST_PIVOT; c.w = 0; c.y = c.z;
+        ctl[t] = c;
+    }
+    if (tid == 0 && s_err) tf[1] = 1;
+}
+
+// back substitution and voltage update; LDS holds only the row publication bytes
+template <typename R, int T, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void split_bs_kernel(KArgs a)
+{
+    extern __shared__ char smem_raw[];
+    __shared__ int s_active[T], s_reset[T];
+    __shared__ int s_any, s_err;
+    __shared__ int s_prog[NW];
+    const DevPlan &P = a.p;
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, t = lane % T, s = lane / T;
+    const bool valid = tile * T + t < a.batch;
+    int4 *ctl = tile_ctl<T>(a, tile);
+    int *tf = reinterpret_cast<int *>(ctl + T);
+    if (!__builtin_amdgcn_readfirstlane(tf[0])) return;
+    unsigned char *done = reinterpret_cast<unsigned char *>(smem_raw);
+    if (tid < T) { s_active[t] = ctl[t].w; s_reset[t] = 0; }
+    if (tid == 0) s_err = 0;
+    if (tid < NW) s_prog[tid] = 0;
+    for (int w = tid; w < P.N; w += NW * 64)
+        __hip_atomic_store(&done[w], (unsigned char)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();
+    if (tid == 0) {
+        int any = 0;
+        for (int q = 0; q < T; q++) any |= s_active[q];
+        s_any = any;
+    }
+    __syncthreads();
+    if (!s_any) return;
+    char *base = a.ws + (size_t)tile * a.tile_bytes;
+    double *vec = reinterpret_cast<double *>(base + a.off_vec);
+    const size_t nT = (size_t)P.n * T;
+    int nprog = 0;
+    // z of the highest positions (the dense tail, solved first) in LDS after the flags
+    R *zlds = reinterpret_cast<R *>(smem_raw + ((P.N + 255) & ~255));
+    const int zb = max(0, P.N - (int)(kBsZBytes / (sizeof(R) * T)));
+    TileCtx<R> cx{a, tid, wave, lane, t, s, valid, reinterpret_cast<R *>(base), reinterpret_cast<R *>(base + a.off_y),
+                  vec, vec + nT, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, done, nullptr, &s_err, s_prog,
+                  nullptr, s_active, s_reset, nprog, zlds, zb};
+    bs_phase<R, T, NW, kWideBs<R>>(cx, true);
+    __syncthreads();
+    if (tid < T && s_active[t]) ctl[t].z += 1;
+    if (tid == 0 && s_err) tf[1] = 1;
+}
+
+// the final convergence decision and the tile layout -> boundary layout
+template <int T>
+__global__ __launch_bounds__(kMBlock) void split_out_kernel(KArgs a)
+{
+    const int tile = blockIdx.x, tid = threadIdx.x, t = tid % T;
+    const int b = tile * T + t;
+    const bool valid = b < a.batch;
+    int4 *ctl = tile_ctl<T>(a, tile);
+    const int *tf = reinterpret_cast<const int *>(ctl + T);
+    if (tid < T && tf[0]) (void)split_decide<T>(a, tile, t);
+    __syncthreads();
+    if (!valid) return;
+    const int n = a.p.n;
+    const double *vec = reinterpret_cast<const double *>(a.ws + (size_t)tile * a.tile_bytes + a.off_vec);
+    const size_t nT = (size_t)n * T;
+    for (int i = tid / T; i < n; i += kMBlock / T) {
+        const size_t o = ((size_t)b * n + i) * 2;
+        a.v_out[o] = vec[i * T + t];
+        a.v_out[o + 1] = vec[nT + i * T + t];
+    }
+    if (tid < T) {
+        const int4 c = ctl[t];
+        const int st = tf[1] ? PF_ST_INTERNAL : c.x;
+        a.iters_out[b] = c.y;
+        a.conv_out[b] = st == PF_ST_CONVERGED ? 1 : 0;
+        if (a.status_out) a.status_out[b] = (int8_t)st;
+    }
+}
+
 // ------------------------------------------------------------------ launch configuration
 struct Config {
-    int precision, tile, waves, schedule, n_long;
+    int precision, tile, waves, schedule, n_long, launch;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct TileLayout {
-    size_t off_y, off_vec, bytes;
+    size_t off_y, off_vec, off_ctl, off_part, bytes;
+    int nbb;
 };
 
+// One tile's block of the workspace: LU values, right-hand sides / steps, the per-bus
+// vectors (|V|, angle, P and Q set points, rectangular V), then for the per-phase launches
+// the instances' states (status, iterations, updates, active) with two tile flags (any
+// instance active, internal error), and the mismatch kernel's per-bus-block maxima.
 static TileLayout tile_layout(const HostPlan &h, const Config &c)
 {
     const size_t rs = c.precision == PF_FP32_LU ? 4 : 8;
     TileLayout L;
     L.off_y = align256((size_t)(h.col_ptr.empty() ? 0 : h.col_ptr[h.N]) * c.tile * rs);
     L.off_vec = L.off_y + align256((size_t)h.N * c.tile * rs);
-    L.bytes = L.off_vec + align256((size_t)6 * h.n * c.tile * 8);
+    L.off_ctl = L.off_vec + align256((size_t)6 * h.n * c.tile * 8);
+    L.off_part = L.off_ctl + align256((size_t)16 * c.tile + 16);
+    L.nbb = (h.n + kMBlock / c.tile - 1) / (kMBlock / c.tile);
+    L.bytes = L.off_part + align256((size_t)L.nbb * c.tile * 12);
     return L;
 }
 
@@ -904,7 +1428,7 @@ static size_t lds_bytes(const HostPlan &h, const Config &c)
 {
     const size_t rs = c.precision == PF_FP32_LU ? 4 : 8;
     return ((size_t)c.waves * 2 * ((size_t)h.slot_rows * c.tile + 2 * c.tile) + (size_t)c.n_long * 2 * h.max_col * c.tile) * rs +
-           (size_t)h.N;
+           (size_t)h.N + (size_t)h.n_longp;
 }
 
 static size_t lds_bytes(const HostPlan &h, const Config &c);
@@ -927,6 +1451,8 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
 {
     c.precision = o ? o->precision : PF_FP64;
     c.schedule = o ? o->schedule : 0;
+    c.launch = o ? o->launch : PF_LAUNCH_AUTO;
+    if (c.launch < PF_LAUNCH_AUTO || c.launch > PF_LAUNCH_PHASES) { err = "launch must be 0, 1 or 2"; return false; }
     if (c.schedule != 0 && c.schedule != 1) { err = "schedule must be 0 or 1"; return false; }
     const int long_slots = o ? o->long_slots : 0;
     if (long_slots < 0 || long_slots > kMaxLong) {
@@ -989,6 +1515,12 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
         c.tile = pick->tile;
         c.waves = pick->waves;
         c.n_long = pick->n_long;
+        // per-phase launches when every tile is resident at once (one generation): there
+        // each phase runs without the fused kernel's spills; with several generations the
+        // fused kernel lets a tile that needs many iterations overlap the other tiles'
+        // work, which a global per-iteration sequence would leave running alone at the end
+        if (c.launch == PF_LAUNCH_AUTO)
+            c.launch = batch > 0 && std::ceil(b / c.tile) <= 256.0 * pick->wg ? PF_LAUNCH_PHASES : PF_LAUNCH_FUSED;
         return true;
     }
     err = "the longest LU column (" + std::to_string(h.max_col) + " entries) does not fit in LDS for any "
@@ -1057,6 +1589,53 @@ static hipError_t launch(const Config &c, const KArgs &a, int grid, size_t lds, 
     }
 }
 
+// The per-phase launches of one solve: layout in, then per iteration the mismatch and
+// Jacobian, the refactorization (with the convergence decision first) and the back
+// substitution, then the final mismatch, decision and layout out.
+template <typename R, int T, int NW>
+static hipError_t launch_phases_t(const KArgs &a, int ntiles, size_t lds, hipStream_t st)
+{
+    auto lu = split_lu_kernel<R, T, NW>;
+    auto bs = split_bs_kernel<R, T, NW>;
+    hipError_t e = allow_lds(lu, lds);
+    const size_t bs_lds = (((size_t)a.p.N + 255) & ~(size_t)255) + kBsZBytes;
+    if (e == hipSuccess) e = allow_lds(bs, bs_lds);
+    if (e != hipSuccess) return e;
+    const int mgrid = std::max(1, std::min(ntiles * a.nbb, 4096));
+    hipLaunchKernelGGL(split_in_kernel<T>, dim3(ntiles), dim3(kMBlock), 0, st, a);
+    for (int k = 0; k < a.max_iter; k++) {
+        hipLaunchKernelGGL(split_v_kernel<T>, dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles);
+        hipLaunchKernelGGL((split_m_kernel<R, T>), dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles, 1);
+        hipLaunchKernelGGL(lu, dim3(ntiles), dim3(NW * 64), lds, st, a);
+        hipLaunchKernelGGL(bs, dim3(ntiles), dim3(NW * 64), bs_lds, st, a);
+    }
+    hipLaunchKernelGGL(split_v_kernel<T>, dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles);
+    hipLaunchKernelGGL((split_m_kernel<R, T>), dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles, 0);
+    hipLaunchKernelGGL(split_out_kernel<T>, dim3(ntiles), dim3(kMBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+#define PF_DISPATCH_PHASES_NW(R, T)                                            \
+    switch (c.waves) {                                                         \
+    case 2: return launch_phases_t<R, T, 2>(a, grid, lds, st);                 \
+    case 4: return launch_phases_t<R, T, 4>(a, grid, lds, st);                 \
+    case 16: return launch_phases_t<R, T, 16>(a, grid, lds, st);               \
+    default: return launch_phases_t<R, T, 8>(a, grid, lds, st);                \
+    }
+
+static hipError_t launch_phases(const Config &c, const KArgs &a, int grid, size_t lds, hipStream_t st)
+{
+    if (c.precision == PF_FP64) {
+        if (c.tile == 4) { PF_DISPATCH_PHASES_NW(double, 4) }
+        if (c.tile == 8) { PF_DISPATCH_PHASES_NW(double, 8) }
+        PF_DISPATCH_PHASES_NW(double, 16)
+    } else {
+        if (c.tile == 8) { PF_DISPATCH_PHASES_NW(float, 8) }
+        if (c.tile == 16) { PF_DISPATCH_PHASES_NW(float, 16) }
+        PF_DISPATCH_PHASES_NW(float, 32)
+    }
+}
+
 static int upload(Plan *pl);
 
 // Validates a solve's arguments and fills its kernel arguments (shared by pf_solve_batch,
@@ -1101,6 +1680,7 @@ static int make_args(Plan *pl, const Config &c, int32_t batch, const double *ybu
     a.tol = tol; a.max_iter = max_iter; a.batch = batch; a.mode = mode;
     a.ws = reinterpret_cast<char *>(workspace);
     a.tile_bytes = L.bytes; a.off_y = L.off_y; a.off_vec = L.off_vec;
+    a.off_ctl = L.off_ctl; a.off_part = L.off_part; a.nbb = L.nbb;
     a.sched = c.schedule;
     // the kernel derives a long panel's slot from its rank with this reciprocal; a count
     // outside 1..kMaxLong (0 only without long panels) would index past the slot counters
@@ -1109,7 +1689,6 @@ static int make_args(Plan *pl, const Config &c, int32_t batch, const double *ybu
         return PF_EINVAL;
     }
     a.n_long = c.n_long;
-    a.n_long_inv = c.n_long >= 2 ? (unsigned)((0x100000000ull + c.n_long - 1) / c.n_long) : 0u;
     a.v_out = v_out; a.iters_out = iters_out; a.conv_out = conv_out; a.status_out = status_out;
     a.aux_out = aux; a.aux2_out = aux2;
     return PF_OK;
@@ -1136,7 +1715,9 @@ static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *
     if (rc != PF_OK) return rc;
     a.v_fb = v_fb;
     a.ybus_stride = ybus_batched ? (size_t)2 * pl->h.nnzy : 0;
-    hipError_t e = launch(c, a, ntiles, lds, reinterpret_cast<hipStream_t>(stream));
+    const bool phases = mode == MODE_SOLVE && !v_fb && c.launch == PF_LAUNCH_PHASES;
+    hipError_t e = phases ? launch_phases(c, a, ntiles, lds, reinterpret_cast<hipStream_t>(stream))
+                          : launch(c, a, ntiles, lds, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) { set_error(std::string("kernel launch failed: ") + hipGetErrorString(e)); return PF_EDEVICE; }
     return PF_OK;
 }
@@ -1182,6 +1763,8 @@ static int scratch_address(void **out)
 // from a row's first entry, and panel descriptors 8 per wavefront, two chunks ahead, so
 // up to 23 * NW (NW <= 16) beyond the last panel.
 constexpr size_t PAD_UPD = 16 * sizeof(Update);
+// the per-phase refactorization reads four rows per sub-lane (SL <= 16) past a column's end
+constexpr size_t PAD_ROWS = 4 * 16;
 constexpr size_t PAD_BS = 64 * sizeof(int32_t);
 constexpr size_t PAD_DESC = 24 * 16 * sizeof(LuPanel);
 static_assert(sizeof(LuPanel) == sizeof(BsPanel), "descriptor tables share one padding");
@@ -1203,12 +1786,13 @@ static int upload(Plan *pl)
     if (hipGetDevice(&pl->device) != hipSuccess) { set_error("no HIP device"); return PF_EDEVICE; }
     DevOffsets off;
     const size_t o_yrp = off.add(h.yrp), o_yci = off.add(h.yci);
-    const size_t o_jpos = off.add(h.jpos), o_isj = off.add(h.isj), o_rel = off.add(h.rel);
+    const size_t o_jpos = off.add(h.jpos), o_isj = off.add(h.isj, PAD_ROWS), o_rel = off.add(h.rel, 4 * PAD_ROWS);
     const size_t o_upd = off.add(h.upd, PAD_UPD);
     const size_t o_bpos = off.add(h.bs_pos, PAD_BS), o_bcol = off.add(h.bs_col, PAD_BS);
     const size_t o_pe = off.add(h.bus_peq), o_qe = off.add(h.bus_qeq);
     const size_t o_perm = off.add(h.perm);
     const size_t o_lud = off.add(h.lu_desc, PAD_DESC), o_bsd = off.add(h.bs_desc, PAD_DESC);
+    const size_t o_ring = off.add(h.ring);
     std::vector<char> host(off.bytes, 0);
     auto put = [&](size_t o, const auto &v) {
         if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * sizeof(v[0]));
@@ -1216,6 +1800,7 @@ static int upload(Plan *pl)
     put(o_yrp, h.yrp); put(o_yci, h.yci); put(o_jpos, h.jpos); put(o_isj, h.isj); put(o_rel, h.rel);
     put(o_upd, h.upd); put(o_bpos, h.bs_pos); put(o_bcol, h.bs_col); put(o_pe, h.bus_peq);
     put(o_qe, h.bus_qeq); put(o_perm, h.perm); put(o_lud, h.lu_desc); put(o_bsd, h.bs_desc);
+    put(o_ring, h.ring);
     void *dm = nullptr;
     if (hipMalloc(&dm, off.bytes) != hipSuccess) { set_error("hipMalloc of the plan failed"); return PF_ENOMEM; }
     if (hipMemcpy(dm, host.data(), off.bytes, hipMemcpyHostToDevice) != hipSuccess) {
@@ -1236,8 +1821,10 @@ static int upload(Plan *pl)
     pl->perm_dev = (const int32_t *)(D + o_perm);
     d.lu_desc = (const LuPanel *)(D + o_lud);
     d.bs_desc = (const BsPanel *)(D + o_bsd);
+    d.ring = (const RingSlot *)(D + o_ring);
     d.n_panels = (int)h.panel_ptr.size() - 1;
     d.slot_rows = h.slot_rows;
+    d.n_longp = h.n_longp;
     return PF_OK;
 }
 
@@ -1607,6 +2194,26 @@ int pf_plan_schedule(pf_plan plan, int32_t order, int32_t *first, int32_t *width
     return PF_OK;
 }
 
+int pf_plan_ring(pf_plan plan, int32_t order, int32_t n_long, int32_t *offset, int32_t *rows, int32_t *wait_lo,
+                 int32_t *wait_hi)
+{
+    Plan *pl = reinterpret_cast<Plan *>(plan);
+    if (!pl || !offset || !rows || !wait_lo || !wait_hi) { set_error("null argument"); return PF_EINVAL; }
+    if (order != 0 && order != 1) { set_error("order must be 0 or 1"); return PF_EINVAL; }
+    if (n_long < 1 || n_long > kMaxLong) { set_error("n_long must be 1.." + std::to_string(kMaxLong)); return PF_EINVAL; }
+    const HostPlan &h = pl->h;
+    for (int r = 0; r < h.n_longp; r++) {
+        const RingSlot &e = h.ring[(((size_t)n_long - 1) * 2 + order) * h.n_longp + r];
+        const int j = h.long_first[(size_t)order * h.n_longp + r];
+        const int w = *std::upper_bound(h.panel_ptr.begin(), h.panel_ptr.end(), j) - j;
+        offset[r] = e.off;
+        rows[r] = w * (h.col_ptr[j + 1] - h.col_ptr[j]);
+        wait_lo[r] = e.blk & 0xffff;
+        wait_hi[r] = e.blk >> 16;
+    }
+    return PF_OK;
+}
+
 size_t pf_workspace_bytes(pf_plan plan, int32_t batch, const pf_solve_opts *opts)
 {
     Plan *pl = reinterpret_cast<Plan *>(plan);
@@ -1631,6 +2238,7 @@ int pf_resolve_opts(pf_plan plan, int32_t batch, const pf_solve_opts *opts, pf_s
     out->waves = c.waves;
     out->schedule = c.schedule;
     out->long_slots = c.n_long;
+    out->launch = c.launch;
     return PF_OK;
 }
 
@@ -1852,6 +2460,7 @@ int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
                     o.waves = w;
                     o.schedule = sc;
                     o.long_slots = ls;
+                    o.launch = PF_LAUNCH_FUSED;      // the form the queue runs
                     Config c;
                     std::string err;
                     if (!resolve_config(pl->h, &o, c, err, batch) || lds_bytes(pl->h, c) > kLdsLimit) continue;

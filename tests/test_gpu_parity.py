@@ -366,7 +366,8 @@ def test_warm_entry_point_restarts_failed_instances(systems):
     v0[0:32, :, 0] = 0.0                                   # non-finite at iteration 0
     v0[32:64, 1:, 1] = 3.0                                 # far-off angles
     for prec in (pf.PF_FP64, pf.PF_FP32_LU):
-        r0 = pf.solve_batch(plan, y, s, vflat, precision=prec)
+        # the warm entry point runs the single fused launch: compared with the same form
+        r0 = pf.solve_batch(plan, y, s, vflat, precision=prec, launch=pf.PF_LAUNCH_FUSED)
         r = pf.solve_batch(plan, y, s, v0, precision=prec, v_fallback=vflat)
         torch.cuda.synchronize()
         for sl in (slice(0, 32), slice(64, 96)):
@@ -501,3 +502,52 @@ def test_zero_pivot_instances_rescued_by_fallback(prec):
             compare_solve(osys, ro, sub, sc.sbus[half])
         else:
             compare_fp32lu(osys, ro, sub, sc.sbus[half])
+
+
+@pytest.mark.parametrize("name,B", [("c0_14bus", 64), ("c4_100bus", 37), ("c1_1350bus", 203), ("c2_9000bus", 77)])
+@pytest.mark.parametrize("prec", [pf.PF_FP64, pf.PF_FP32_LU])
+def test_per_phase_launches_match_oracle(systems, name, B, prec):
+    """The per-phase launch sequence (mismatch/Jacobian kernel over all buses and instances,
+    refactorization and back-substitution kernels per tile, the loop on the host) against
+    the oracle, on ragged batches: the FP64 full-solve bar, or the FP32-LU bar.  It agrees
+    with the single fused launch in every flag, status and iteration count, and in V to
+    rounding (the kernels round the rectangular voltages' products in another order)."""
+    g, yb, osys, plan = systems[name]
+    sc = gg.make_scenarios(g, B, 4242, "uniform20" if name == "c0_14bus" else "mc")
+    y, s, v = to_dev(yb, sc)
+    rp = pf.solve_batch(plan, y, s, v, precision=prec, launch=pf.PF_LAUNCH_PHASES)
+    rf = pf.solve_batch(plan, y, s, v, precision=prec, launch=pf.PF_LAUNCH_FUSED)
+    torch.cuda.synchronize()
+    ro = osys.solve(sc.sbus, sc.v0)
+    if prec == pf.PF_FP64:
+        compare_solve(osys, ro, rp, sc.sbus)
+    else:
+        compare_fp32lu(osys, ro, rp, sc.sbus, name=name)
+    for f in ("iters", "converged", "status"):
+        assert torch.equal(getattr(rp, f), getattr(rf, f)), f
+    conv = rp.converged.bool()
+    if bool(conv.any()):
+        assert (rp.v[conv] - rf.v[conv]).abs().max().item() <= (1e-9 if prec == pf.PF_FP64 else 1e-7)
+
+
+@pytest.mark.parametrize("max_iter", [0, 1, 3])
+def test_per_phase_launches_iteration_limits_and_single_instance(systems, max_iter):
+    """Iteration limits (no update, one, three) and a batch of one through the per-phase
+    launches: the same flags, statuses and iteration counts as the fused launch, and the
+    oracle's where it converges."""
+    g, yb, osys, plan = systems["c1_1350bus"]
+    sc = gg.make_scenarios(g, 9, 4343, "mc")
+    y, s9, v9 = to_dev(yb, sc)
+    for B in (9, 1):
+        s = s9[:B].contiguous()
+        v = v9[:B].contiguous()
+        rp = pf.solve_batch(plan, y, s, v, max_iter=max_iter, launch=pf.PF_LAUNCH_PHASES)
+        rf = pf.solve_batch(plan, y, s, v, max_iter=max_iter, launch=pf.PF_LAUNCH_FUSED)
+        torch.cuda.synchronize()
+        for f in ("iters", "converged", "status"):
+            assert torch.equal(getattr(rp, f), getattr(rf, f)), (B, f)
+        ro = osys.solve(sc.sbus[:B], sc.v0[:B], max_iter=max_iter)
+        assert np.array_equal(rp.converged.cpu().numpy().astype(bool), ro.converged)
+        assert np.array_equal(rp.iters.cpu().numpy(), ro.iters)
+        if max_iter == 0:
+            assert np.array_equal(rp.v.cpu().numpy(), sc.v0[:B])

@@ -252,6 +252,9 @@ def test_automatic_launch_configuration():
     g1 = gg.grid("c1_1350bus")
     p1 = pf.Plan.from_ybus(gg.ybus(g1), g1.bus_type)
     assert (p1.resolve(10000)["tile"], p1.resolve(10000)["waves"]) == (8, 16)
+    # several generations of tiles: one fused launch; one generation: per-phase launches
+    assert p1.resolve(10000)["launch"] == pf.PF_LAUNCH_FUSED
+    assert p1.resolve(10000, launch=pf.PF_LAUNCH_PHASES)["launch"] == pf.PF_LAUNCH_PHASES
     r = p1.resolve(10000, precision=pf.PF_FP32_LU)
     assert (r["tile"], r["waves"]) == (16, 16)
     r = p1.resolve(10000, tile=4, waves=2, schedule=1)
@@ -260,6 +263,7 @@ def test_automatic_launch_configuration():
     p2 = pf.Plan.from_ybus(gg.ybus(g2), g2.bus_type)
     r = p2.resolve(2000)
     assert (r["tile"], r["waves"]) == (8, 16)
+    assert r["launch"] == pf.PF_LAUNCH_PHASES            # 250 tiles: one generation
     # long slots: as many as keep the resident workgroups the batch can use.  Measured on
     # 10,000 scenarios of the 1350-bus grid: FP64 (8, 8) 31.4 / 29.1 / 27.6 ms with 2 / 3 /
     # 4 slots, (8, 16) with 8 slots 26.2 ms; FP32-LU (16, 8) 23.9 ms, (16, 16) with 8
@@ -283,3 +287,37 @@ def test_automatic_launch_configuration():
                 dict(long_slots=-1)):
         with pytest.raises(pf.PfError):
             p1.resolve(100, **bad)
+
+
+@pytest.mark.parametrize("name", ["c1_1350bus", "c2_9000bus", "c4_3000bus"])
+@pytest.mark.parametrize("order", [0, 1])
+def test_long_panel_ring_never_reuses_rows_in_use(name, order):
+    """The long panels' working columns share an LDS ring of n_long * 2 * max_col rows.
+    A panel may start once every rank in its wait range has published; a panel that
+    started has seen every rank its waits published before.  Safety: for every pair of
+    long panels r' < r whose rows overlap, r' must be among the ranks guaranteed published
+    when r starts (its wait range, and, transitively, theirs).  Liveness: waits only name
+    earlier ranks.  Checked for every budget from the ring's own rows and offsets."""
+    g = gg.grid(name)
+    plan = pf.Plan.from_ybus(gg.ybus(g), g.bus_type)
+    cp, _, _ = plan.lu_pattern()
+    first, width, rank, _ = plan.schedule(order)
+    long_q = np.flatnonzero(rank >= 0)
+    size_expected = width[long_q] * (cp[first[long_q] + 1] - cp[first[long_q]])
+    max_col = plan.info["max_col"]
+    for n_long in range(1, 13):
+        off, rows, lo, hi = plan.ring(order, n_long)
+        cap = n_long * 2 * max_col
+        assert np.array_equal(rows, size_expected)
+        assert (off >= 0).all() and (off + rows <= cap).all()
+        guaranteed = []
+        for r in range(len(off)):
+            assert lo[r] > hi[r] or (0 <= lo[r] and hi[r] < r)       # waits name earlier ranks only
+            g_r = set()
+            for b in range(lo[r], hi[r] + 1):
+                g_r.add(b)
+                g_r |= guaranteed[b]
+            guaranteed.append(g_r)
+            for rp in range(r):
+                if off[rp] < off[r] + rows[r] and off[r] < off[rp] + rows[rp]:
+                    assert rp in g_r, (n_long, r, rp)
