@@ -35,13 +35,14 @@ WORKLOADS = {
 }
 
 
-PROFILE = os.path.join(ROOT, "profiles", "nr_tile_kernel_c1_1350bus_10000_fp64.md")
+PROFILE = os.path.join(ROOT, "profiles", "solver_c1_1350bus_10000_fp64.md")
 
 
 def measured_traffic():
-    """HBM bytes per launch of the default workload from the committed profiler summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), or None when the solver
-    source has changed since the counters were taken."""
+    """HBM bytes per solve of the default workload from the committed profiler summary
+    (FETCH_SIZE + WRITE_SIZE of the solver kernels, scaled by a copy that reads 64-byte
+    segments like the solver), or None when the solver source has changed since the
+    counters were taken."""
     import hashlib
     try:
         text = open(PROFILE).read()

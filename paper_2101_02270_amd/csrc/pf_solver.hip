@@ -49,8 +49,13 @@ enum Mode { MODE_SOLVE = 0, MODE_MISMATCH = 1, MODE_FACTOR = 2, MODE_STEP = 3 };
 
 constexpr int kMBlock = 256;     // threads of a mismatch-kernel workgroup (per-phase launches)
 constexpr size_t kBsZBytes = 48 * 1024;   // per-phase back substitution: LDS for z of the tail
+constexpr int kPhasesMinLu = 10000;       // automatic launch form: per-phase from this many LU entries
 constexpr int UPD_GROUP = 3;     // column updates whose operand loads are issued together
 constexpr int L_ROWS = 2;        // rows of each source column per lane loaded with its group
+// the same, and the panel rows prefetched per lane, in the per-phase refactorization kernel
+// (measured there: four updates per group 1-2% faster than three or five; three or four
+// source rows per lane, or three prefetched panel rows, 1-5% slower)
+constexpr int kWideGroup = 4, kWideLRows = 2, kWideARows = 2;
 
 struct KArgs {
     DevPlan p;
@@ -200,7 +205,11 @@ __device__ __forceinline__ void lu_phase(TileCtx<R> &cx)
 {
     constexpr int SL = 64 / T;
     constexpr int NT = NW * 64;
-    constexpr int A_ROWS = 2;            // panel rows per lane whose loads are issued together
+    // panel rows per lane whose loads are issued together; updates per operand group and
+    // rows of each source column per lane loaded with it (more in the per-phase kernel)
+    constexpr int A_ROWS = WIDE ? kWideARows : 2;
+    constexpr int UG = WIDE ? kWideGroup : UPD_GROUP;
+    constexpr int LR = WIDE ? kWideLRows : L_ROWS;
     const KArgs &a = cx.a;
     const DevPlan &P = a.p;
     const int tid = cx.tid, wave = cx.wave, lane = cx.lane, t = cx.t, s = cx.s;
@@ -371,10 +380,10 @@ __device__ __forceinline__ void lu_phase(TileCtx<R> &cx)
         pdc = pdn;
         // Updates in ascending source order.  After waiting for the first pending source,
         // the run of following updates whose sources are already published (up to
-        // UPD_GROUP, within one chunk of records) has its operand loads issued together
-        // (L_ROWS rows of each source column per lane), then the updates are applied one
+        // UG, within one chunk of records) has its operand loads issued together
+        // (LR rows of each source column per lane), then the updates are applied one
         // after another in LDS (the order of the arithmetic is unchanged).  Rows beyond
-        // L_ROWS per lane (the long source columns of the dense tail) are loaded two at a
+        // LR per lane (the long source columns of the dense tail) are loaded two at a
         // time.
         const int u0 = pd.u0, u1 = pd.u1;
         int ubase = u0, uc0 = ucur, uc1 = 0;
@@ -394,12 +403,12 @@ __device__ __forceinline__ void lu_phase(TileCtx<R> &cx)
                 uc0 = uc1;
                 if (u1 - ubase > 16) uc1 = upd_chunk_at(ubase + 16);
             }
-            Update ups[UPD_GROUP];
+            Update ups[UG];
             ups[0] = upd_rec(ub);
             wait_published<NW>(done, ups[0].k, s_prog, err);
             int gcnt = 1;
 #pragma unroll
-            for (int g = 1; g < UPD_GROUP; g++) {
+            for (int g = 1; g < UG; g++) {
                 if (gcnt == g && ub + g < u1 && ub + g - ubase < 16) {
                     ups[g] = upd_rec(ub + g);
                     const int f = __builtin_amdgcn_readfirstlane((int)__hip_atomic_load(
@@ -408,17 +417,17 @@ __device__ __forceinline__ void lu_phase(TileCtx<R> &cx)
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            R lv[UPD_GROUP][L_ROWS], yk[UPD_GROUP];
-            int rv[UPD_GROUP][L_ROWS];
+            R lv[UG][LR], yk[UG];
+            int rv[UG][LR];
 #pragma unroll
-            for (int g = 0; g < UPD_GROUP; g++) {
+            for (int g = 0; g < UG; g++) {
                 yk[g] = 0;
 #pragma unroll
-                for (int e = 0; e < L_ROWS; e++) { lv[g][e] = 0; rv[g][e] = -1; }
+                for (int e = 0; e < LR; e++) { lv[g][e] = 0; rv[g][e] = -1; }
                 if (g < gcnt) {
                     const int lcnt = ups[g].krel_lcnt >> 16;
 #pragma unroll
-                    for (int e = 0; e < L_ROWS; e++)
+                    for (int e = 0; e < LR; e++)
                         if (s + e * SL < lcnt) {
                             lv[g][e] = LU[(size_t)(ups[g].lbeg + s + e * SL) * T + t];
                             rv[g][e] = P.rel[ups[g].roff + s + e * SL];
@@ -428,7 +437,7 @@ __device__ __forceinline__ void lu_phase(TileCtx<R> &cx)
             }
             wave_sync();
 #pragma unroll
-            for (int g = 0; g < UPD_GROUP; g++) {
+            for (int g = 0; g < UG; g++) {
                 if (g < gcnt) {
                     const Update up = ups[g];
                     const int krel = up.krel_lcnt & 0xffff, lcnt = up.krel_lcnt >> 16;
@@ -444,12 +453,12 @@ __device__ __forceinline__ void lu_phase(TileCtx<R> &cx)
                         else if (two && tr == dr + 1) ysl1[t] = fma(-l, ykg, ysl1[t]);
                     };
 #pragma unroll
-                    for (int e = 0; e < L_ROWS; e++)
+                    for (int e = 0; e < LR; e++)
                         if (rv[g][e] >= 0) apply(rv[g][e], lv[g][e]);
                     if constexpr (WIDE) {
                         // rows past the column's end read the following entries and the
                         // padded target table, and are discarded
-                        for (int r = s + L_ROWS * SL; r < lcnt; r += 4 * SL) {
+                        for (int r = s + LR * SL; r < lcnt; r += 4 * SL) {
                             R lx[4];
                             int tx[4];
 #pragma unroll
@@ -462,7 +471,7 @@ __device__ __forceinline__ void lu_phase(TileCtx<R> &cx)
                                 if (r + x * SL < lcnt) apply(tx[x], lx[x]);
                         }
                     } else {
-                        for (int r = s + L_ROWS * SL; r < lcnt; r += 2 * SL) {
+                        for (int r = s + LR * SL; r < lcnt; r += 2 * SL) {
                             const bool h2 = r + SL < lcnt;
                             const R l = LU[(size_t)(up.lbeg + r) * T + t];
                             const int tr = P.rel[up.roff + r];
@@ -1088,10 +1097,23 @@ __global__ void queue_reset_kernel(int *counters, int n, unsigned long long *t0)
 template <typename R> constexpr bool kWideLu = true;
 template <typename R> constexpr bool kWideBs = false;
 
+// A tile's control block: per instance {status, iterations, updates, active}, the tile's
+// flags {any active, internal error}, per instance the fallback start's state {retried,
+// restart pending, updates when the current attempt began}, and the last max |F|.
 template <int T>
 __device__ __forceinline__ int4 *tile_ctl(const KArgs &a, int tile)
 {
     return reinterpret_cast<int4 *>(a.ws + (size_t)tile * a.tile_bytes + a.off_ctl);
+}
+template <int T>
+__device__ __forceinline__ int4 *tile_warm(const KArgs &a, int tile)
+{
+    return tile_ctl<T>(a, tile) + T + 1;
+}
+template <int T>
+__device__ __forceinline__ double *tile_prevf(const KArgs &a, int tile)
+{
+    return reinterpret_cast<double *>(tile_ctl<T>(a, tile) + 2 * T + 1);
 }
 
 // boundary layout [B][n][2] -> tile layout; instance states and tile flags initialised
@@ -1115,7 +1137,11 @@ __global__ __launch_bounds__(kMBlock) void split_in_kernel(KArgs a)
         vec[2 * nT + i * T + t] = ps; vec[3 * nT + i * T + t] = qs;
     }
     int4 *ctl = tile_ctl<T>(a, tile);
-    if (tid < T) ctl[t] = make_int4(PF_ST_MAXITER, 0, 0, valid ? 1 : 0);
+    if (tid < T) {
+        ctl[t] = make_int4(PF_ST_MAXITER, 0, 0, valid ? 1 : 0);
+        tile_warm<T>(a, tile)[t] = make_int4(0, 0, 0, 0);
+        tile_prevf<T>(a, tile)[t] = INFINITY;
+    }
     if (tid == 0) {
         int *tf = reinterpret_cast<int *>(ctl + T);
         tf[0] = tile * T < a.batch ? 1 : 0;
@@ -1141,6 +1167,13 @@ __global__ __launch_bounds__(kMBlock) void split_v_kernel(KArgs a, int ntiles)
         if (i >= n) continue;
         double *vec = reinterpret_cast<double *>(base + a.off_vec);
         double2 *Vc = reinterpret_cast<double2 *>(vec + 4 * nT);
+        // an instance whose first attempt failed restarts from the fallback point
+        const int b = tile * T + t;
+        if (a.v_fb && b < a.batch && tile_warm<T>(a, tile)[t].y) {
+            const size_t o = ((size_t)b * n + i) * 2;
+            vec[i * T + t] = a.v_fb[o];
+            vec[nT + i * T + t] = a.v_fb[o + 1];
+        }
         double sn, cs;
         const double vm = vec[i * T + t];
         sincos_angle(vec[nT + i * T + t], &sn, &cs);
@@ -1241,27 +1274,40 @@ __global__ __launch_bounds__(kMBlock) void split_m_kernel(KArgs a, int ntiles, i
     }
 }
 
-// The convergence decision of instance t of a tile from the mismatch kernel's maxima (the
-// same rule as nr_tile_body: non-finite, below tol, or max_iter updates done); called by the
-// tile's first T threads.  Returns whether the instance stays active.
+// The convergence decision of instance t of a tile from the mismatch kernel's maxima, the
+// rule of nr_tile_body: non-finite, below tol, or max_iter updates done in the current
+// attempt; with a fallback start, a first attempt also ends when an update did not reduce
+// max |F|, and a failed first attempt restarts from the fallback point (the V kernel of the
+// next iteration reloads it) instead of ending.  Called by the tile's first T threads;
+// returns whether the instance stays active and in *reset whether it restarts.
 template <int T>
-__device__ __forceinline__ int split_decide(const KArgs &a, int tile, int t)
+__device__ __forceinline__ int split_decide(const KArgs &a, int tile, int t, int *reset)
 {
     int4 *ctl = tile_ctl<T>(a, tile);
     int4 c = ctl[t];
+    int4 w = tile_warm<T>(a, tile)[t];
+    w.y = 0;                                        // a pending restart has been reloaded
     if (c.w) {
         const double *pm = reinterpret_cast<const double *>(a.ws + (size_t)tile * a.tile_bytes + a.off_part);
         const int *pb = reinterpret_cast<const int *>(pm + (size_t)a.nbb * T);
         double nf = 0.0;
         int nb = 0;
         for (int k = 0; k < a.nbb; k++) { nf = fmax(nf, pm[k * T + t]); nb |= pb[k * T + t]; }
+        double *pfp = tile_prevf<T>(a, tile) + t;
         int fail = 0;
         if (nb) fail = PF_ST_NONFINITE;
         else if (nf < a.tol) { c.x = PF_ST_CONVERGED; c.w = 0; c.y = c.z; }
-        else if (c.z >= a.max_iter) fail = PF_ST_MAXITER;
-        if (fail) { c.x = fail; c.w = 0; c.y = c.z; }
+        else if (c.z - w.z >= a.max_iter) fail = PF_ST_MAXITER;
+        else if (a.v_fb && !w.x && !(nf < *pfp)) fail = PF_ST_MAXITER;
+        *pfp = nf;
+        if (fail) {
+            if (a.v_fb && !w.x) { w.x = 1; w.y = 1; w.z = c.z; }
+            else { c.x = fail; c.w = 0; c.y = c.z; }
+        }
         ctl[t] = c;
     }
+    tile_warm<T>(a, tile)[t] = w;
+    *reset = w.y;
     return c.w;
 }
 
@@ -1282,9 +1328,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
     int *tf = reinterpret_cast<int *>(ctl + T);
     if (!__builtin_amdgcn_readfirstlane(tf[0])) return;
     if (tid < T) {
-        s_active[t] = split_decide<T>(a, tile, t);
+        int rs = 0;
+        s_active[t] = split_decide<T>(a, tile, t, &rs);
         s_piv[t] = 0;
-        s_reset[t] = 0;
+        s_reset[t] = rs;
     }
     if (tid == 0) s_err = 0;
     if (tid < NW) s_prog[tid] = 0;
@@ -1312,10 +1359,16 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
                   s_prog, s_piv, s_active, s_reset, nprog, nullptr, P.N};
     lu_phase<R, T, NW, kWideLu<R>>(cx);
     __syncthreads();
-    if (tid < T && s_piv[t] && s_active[t]) {
+    if (tid < T && s_piv[t] && s_active[t] && !s_reset[t]) {
         int4 c = ctl[t];
-        c.x = PF_ST_PIVOT; c.w = 0; c.y = c.z;
-        ctl[t] = c;
+        int4 w = tile_warm<T>(a, tile)[t];
+        if (a.v_fb && !w.x) {
+            w.x = 1; w.y = 1; w.z = c.z;
+            tile_warm<T>(a, tile)[t] = w;
+        } else {
+            c.x = PF_ST_PIVOT; c.w = 0; c.y = c.z;
+            ctl[t] = c;
+        }
     }
     if (tid == 0 && s_err) tf[1] = 1;
 }
@@ -1337,7 +1390,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
     int *tf = reinterpret_cast<int *>(ctl + T);
     if (!__builtin_amdgcn_readfirstlane(tf[0])) return;
     unsigned char *done = reinterpret_cast<unsigned char *>(smem_raw);
-    if (tid < T) { s_active[t] = ctl[t].w; s_reset[t] = 0; }
+    if (tid < T) { s_active[t] = ctl[t].w; s_reset[t] = tile_warm<T>(a, tile)[t].y; }
     if (tid == 0) s_err = 0;
     if (tid < NW) s_prog[tid] = 0;
     for (int w = tid; w < P.N; w += NW * 64)
@@ -1362,7 +1415,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
                   nullptr, s_active, s_reset, nprog, zlds, zb};
     bs_phase<R, T, NW, kWideBs<R>>(cx, true);
     __syncthreads();
-    if (tid < T && s_active[t]) ctl[t].z += 1;
+    if (tid < T && s_active[t] && !s_reset[t]) ctl[t].z += 1;
     if (tid == 0 && s_err) tf[1] = 1;
 }
 
@@ -1375,7 +1428,14 @@ __global__ __launch_bounds__(kMBlock) void split_out_kernel(KArgs a)
     const bool valid = b < a.batch;
     int4 *ctl = tile_ctl<T>(a, tile);
     const int *tf = reinterpret_cast<const int *>(ctl + T);
-    if (tid < T && tf[0]) (void)split_decide<T>(a, tile, t);
+    if (tid < T && tf[0]) {
+        int rs = 0;
+        if (split_decide<T>(a, tile, t, &rs) && rs) {
+            // a restart requested at the last decision has no iteration left
+            int4 *c = tile_ctl<T>(a, tile) + t;
+            c->x = PF_ST_MAXITER; c->w = 0; c->y = c->z;
+        }
+    }
     __syncthreads();
     if (!valid) return;
     const int n = a.p.n;
@@ -1418,7 +1478,7 @@ static TileLayout tile_layout(const HostPlan &h, const Config &c)
     L.off_y = align256((size_t)(h.col_ptr.empty() ? 0 : h.col_ptr[h.N]) * c.tile * rs);
     L.off_vec = L.off_y + align256((size_t)h.N * c.tile * rs);
     L.off_ctl = L.off_vec + align256((size_t)6 * h.n * c.tile * 8);
-    L.off_part = L.off_ctl + align256((size_t)16 * c.tile + 16);
+    L.off_part = L.off_ctl + align256((size_t)40 * c.tile + 16);
     L.nbb = (h.n + kMBlock / c.tile - 1) / (kMBlock / c.tile);
     L.bytes = L.off_part + align256((size_t)L.nbb * c.tile * 12);
     return L;
@@ -1515,12 +1575,13 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
         c.tile = pick->tile;
         c.waves = pick->waves;
         c.n_long = pick->n_long;
-        // per-phase launches when every tile is resident at once (one generation): there
-        // each phase runs without the fused kernel's spills; with several generations the
-        // fused kernel lets a tile that needs many iterations overlap the other tiles'
-        // work, which a global per-iteration sequence would leave running alone at the end
+        // per-phase launches for grids whose iterations are long against a launch (at least
+        // 10,000 LU entries): each phase runs without the fused kernel's spills, and a
+        // batch of several generations of tiles is cut into one-generation chunks on
+        // concurrent streams.  Small grids keep the single fused launch, where three
+        // launches per iteration would cost more than the phases gain.
         if (c.launch == PF_LAUNCH_AUTO)
-            c.launch = batch > 0 && std::ceil(b / c.tile) <= 256.0 * pick->wg ? PF_LAUNCH_PHASES : PF_LAUNCH_FUSED;
+            c.launch = h.col_ptr[h.N] >= kPhasesMinLu ? PF_LAUNCH_PHASES : PF_LAUNCH_FUSED;
         return true;
     }
     err = "the longest LU column (" + std::to_string(h.max_col) + " entries) does not fit in LDS for any "
@@ -1603,7 +1664,10 @@ static hipError_t launch_phases_t(const KArgs &a, int ntiles, size_t lds, hipStr
     if (e != hipSuccess) return e;
     const int mgrid = std::max(1, std::min(ntiles * a.nbb, 4096));
     hipLaunchKernelGGL(split_in_kernel<T>, dim3(ntiles), dim3(kMBlock), 0, st, a);
-    for (int k = 0; k < a.max_iter; k++) {
+    // with a fallback start, the attempts' updates and the restart's decision take at most
+    // 2 max_iter + 1 iterations
+    const int iters = a.v_fb ? 2 * a.max_iter + 1 : a.max_iter;
+    for (int k = 0; k < iters; k++) {
         hipLaunchKernelGGL(split_v_kernel<T>, dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles);
         hipLaunchKernelGGL((split_m_kernel<R, T>), dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles, 1);
         hipLaunchKernelGGL(lu, dim3(ntiles), dim3(NW * 64), lds, st, a);
@@ -1694,11 +1758,78 @@ static int make_args(Plan *pl, const Config &c, int32_t batch, const double *ybu
     return PF_OK;
 }
 
+// Per-phase launches over a batch of several generations of tiles: the batch is cut into
+// chunks of one generation each, and the chunks' launch sequences go to a small pool of
+// streams (default priority) that start after the caller's stream and that the caller's
+// stream waits for.  A chunk whose instances need many iterations then overlaps the
+// other chunks' work instead of running alone after them.  The pool and its events are
+// created once per device and kept; `pooled` = false (the allocation-free entry point)
+// keeps everything on the caller's stream.
+constexpr int kPhaseStreams = 4;
+struct PhasePool {
+    hipStream_t st[kPhaseStreams] = {};
+    hipEvent_t start = nullptr, fin[kPhaseStreams] = {};
+    int cus = 0;
+    bool ready = false;
+};
+static std::mutex g_pool_mu;
+static PhasePool g_pool[64];
+
+static hipError_t launch_phases_chunked(const Config &c, const KArgs &a, int ntiles, size_t lds, hipStream_t user,
+                                        bool pooled)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (!pooled || dev < 0 || dev >= 64) return launch_phases(c, a, ntiles, lds, user);
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    PhasePool &pp = g_pool[dev];
+    if (!pp.ready) {
+        if ((e = hipDeviceGetAttribute(&pp.cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        for (int i = 0; i < kPhaseStreams; i++) {
+            if ((e = hipStreamCreateWithFlags(&pp.st[i], hipStreamNonBlocking)) != hipSuccess) return e;
+            if ((e = hipEventCreateWithFlags(&pp.fin[i], hipEventDisableTiming)) != hipSuccess) return e;
+        }
+        if ((e = hipEventCreateWithFlags(&pp.start, hipEventDisableTiming)) != hipSuccess) return e;
+        pp.ready = true;
+    }
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(kLdsLimit / std::max<size_t>(lds, 1), 16 / c.waves));
+    const int gen = std::max(1, pp.cus * per_cu);
+    const int nchunk = (ntiles + gen - 1) / gen;
+    if (nchunk <= 1) return launch_phases(c, a, ntiles, lds, user);
+    const int ns = std::min(nchunk, kPhaseStreams);
+    if ((e = hipEventRecord(pp.start, user)) != hipSuccess) return e;
+    for (int i = 0; i < ns; i++)
+        if ((e = hipStreamWaitEvent(pp.st[i], pp.start, 0)) != hipSuccess) return e;
+    const size_t n2 = (size_t)2 * a.p.n;
+    for (int ci = 0; ci < nchunk; ci++) {
+        const int t0 = ci * gen, nt = std::min(gen, ntiles - t0);
+        const size_t b0 = (size_t)t0 * c.tile;
+        KArgs ac = a;
+        ac.batch = (int)std::min<size_t>((size_t)a.batch - b0, (size_t)nt * c.tile);
+        ac.ws = a.ws + (size_t)t0 * a.tile_bytes;
+        ac.sbus = a.sbus + b0 * n2;
+        ac.v0 = a.v0 + b0 * n2;
+        if (a.v_fb) ac.v_fb = a.v_fb + b0 * n2;
+        ac.ybus = a.ybus + b0 * a.ybus_stride;
+        ac.v_out = a.v_out + b0 * n2;
+        ac.iters_out = a.iters_out + b0;
+        ac.conv_out = a.conv_out + b0;
+        if (a.status_out) ac.status_out = a.status_out + b0;
+        if ((e = launch_phases(c, ac, nt, lds, pp.st[ci % ns])) != hipSuccess) return e;
+    }
+    for (int i = 0; i < ns; i++) {
+        if ((e = hipEventRecord(pp.fin[i], pp.st[i])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(user, pp.fin[i], 0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *sbus, const double *v0,
                double tol, int32_t max_iter, const pf_solve_opts *opts, void *workspace,
                size_t workspace_bytes, int mode, double *v_out, int32_t *iters_out, uint8_t *conv_out,
                int8_t *status_out, double *aux, double *aux2, void *stream, const double *v_fb = nullptr,
-               int ybus_batched = 0)
+               int ybus_batched = 0, bool pooled = true)
 {
     Plan *pl = reinterpret_cast<Plan *>(plan_h);
     if (!pl) { set_error("null plan"); return PF_EINVAL; }
@@ -1715,8 +1846,8 @@ static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *
     if (rc != PF_OK) return rc;
     a.v_fb = v_fb;
     a.ybus_stride = ybus_batched ? (size_t)2 * pl->h.nnzy : 0;
-    const bool phases = mode == MODE_SOLVE && !v_fb && c.launch == PF_LAUNCH_PHASES;
-    hipError_t e = phases ? launch_phases(c, a, ntiles, lds, reinterpret_cast<hipStream_t>(stream))
+    const bool phases = mode == MODE_SOLVE && c.launch == PF_LAUNCH_PHASES;
+    hipError_t e = phases ? launch_phases_chunked(c, a, ntiles, lds, reinterpret_cast<hipStream_t>(stream), pooled)
                           : launch(c, a, ntiles, lds, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) { set_error(std::string("kernel launch failed: ") + hipGetErrorString(e)); return PF_EDEVICE; }
     return PF_OK;
@@ -2277,7 +2408,7 @@ int pf_solve_batch_noalloc(pf_plan plan, int32_t batch, const double *ybus, int3
     const int rc = scratch_address(&ws);
     if (rc != PF_OK) return rc;
     return run(plan, batch, ybus, sbus, v0, tol, max_iter, opts, ws, kScratchBytes, MODE_SOLVE, v_out, iters_out,
-               converged_out, status_out, nullptr, nullptr, stream, nullptr, ybus_batched);
+               converged_out, status_out, nullptr, nullptr, stream, nullptr, ybus_batched, false);
 }
 
 int pf_solve_batch_warm(pf_plan plan, int32_t batch, const double *ybus, int32_t ybus_batched,

@@ -551,3 +551,28 @@ def test_per_phase_launches_iteration_limits_and_single_instance(systems, max_it
         assert np.array_equal(rp.iters.cpu().numpy(), ro.iters)
         if max_iter == 0:
             assert np.array_equal(rp.v.cpu().numpy(), sc.v0[:B])
+
+
+@pytest.mark.parametrize("prec", [pf.PF_FP64, pf.PF_FP32_LU])
+@pytest.mark.parametrize("max_iter", [1, 3, 10])
+def test_warm_start_per_phase_equals_fused(systems, prec, max_iter):
+    """pf_solve_batch_warm in the per-phase launch form against the fused kernel on the
+    1350-bus grid: starts with |V| = 0 (non-finite at once: restart), far-off angles (the
+    attempt stops improving: restart, or converges elsewhere), and good starts, under
+    several iteration limits.  Same flags, statuses, iteration counts and V, bit for bit
+    (the restart rules and their budgets are the same in both forms)."""
+    g, yb, osys, plan = systems["c1_1350bus"]
+    sc = gg.make_scenarios(g, 72, 33, "mc")
+    y, s, vflat = to_dev(yb, sc)
+    v0 = vflat.clone()
+    v0[0:24, :, 0] = 0.0
+    v0[24:48, 1:, 1] = 3.0
+    rf = pf.solve_batch(plan, y, s, v0, precision=prec, max_iter=max_iter, v_fallback=vflat,
+                        launch=pf.PF_LAUNCH_FUSED)
+    rp = pf.solve_batch(plan, y, s, v0, precision=prec, max_iter=max_iter, v_fallback=vflat,
+                        launch=pf.PF_LAUNCH_PHASES)
+    torch.cuda.synchronize()
+    for f in ("v", "iters", "converged", "status"):
+        assert torch.equal(getattr(rp, f), getattr(rf, f)), f
+    if max_iter == 10:
+        assert bool(rp.converged[0:24].all()) and bool(rp.converged[48:].all())

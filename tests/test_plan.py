@@ -252,9 +252,12 @@ def test_automatic_launch_configuration():
     g1 = gg.grid("c1_1350bus")
     p1 = pf.Plan.from_ybus(gg.ybus(g1), g1.bus_type)
     assert (p1.resolve(10000)["tile"], p1.resolve(10000)["waves"]) == (8, 16)
-    # several generations of tiles: one fused launch; one generation: per-phase launches
-    assert p1.resolve(10000)["launch"] == pf.PF_LAUNCH_FUSED
-    assert p1.resolve(10000, launch=pf.PF_LAUNCH_PHASES)["launch"] == pf.PF_LAUNCH_PHASES
+    # grids of at least 10,000 LU entries: per-phase launches; small grids: one fused launch
+    assert p1.resolve(10000)["launch"] == pf.PF_LAUNCH_PHASES
+    assert p1.resolve(10000, launch=pf.PF_LAUNCH_FUSED)["launch"] == pf.PF_LAUNCH_FUSED
+    g0 = gg.grid("c0_14bus")
+    p0 = pf.Plan.from_ybus(gg.ybus(g0), g0.bus_type)
+    assert p0.resolve(64)["launch"] == pf.PF_LAUNCH_FUSED
     r = p1.resolve(10000, precision=pf.PF_FP32_LU)
     assert (r["tile"], r["waves"]) == (16, 16)
     r = p1.resolve(10000, tile=4, waves=2, schedule=1)
@@ -263,7 +266,7 @@ def test_automatic_launch_configuration():
     p2 = pf.Plan.from_ybus(gg.ybus(g2), g2.bus_type)
     r = p2.resolve(2000)
     assert (r["tile"], r["waves"]) == (8, 16)
-    assert r["launch"] == pf.PF_LAUNCH_PHASES            # 250 tiles: one generation
+    assert r["launch"] == pf.PF_LAUNCH_PHASES
     # long slots: as many as keep the resident workgroups the batch can use.  Measured on
     # 10,000 scenarios of the 1350-bus grid: FP64 (8, 8) 31.4 / 29.1 / 27.6 ms with 2 / 3 /
     # 4 slots, (8, 16) with 8 slots 26.2 ms; FP32-LU (16, 8) 23.9 ms, (16, 16) with 8
