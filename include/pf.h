@@ -84,9 +84,21 @@ typedef struct {
                               instances, refactorization per tile, back substitution per
                               tile), each with its own register budget.  Same results.
                               pf_solve_batch only; the other entry points run fused        */
-    int32_t reserved[2];
+    int32_t reorder;       /* PF_REORDER_AUTO (0): per-phase solves of several generations of
+                              tiles run the first update over the whole batch, then order
+                              the instances by the size of their first step, largest first:
+                              the hardest finish in one fused launch of small tiles that
+                              keep their CUs (their long iteration chains run at one tile's
+                              latency beside the rest), the others in dense tiles.  Needs
+                              the workspace size pf_workspace_bytes gives, else the
+                              caller's order is kept.  PF_REORDER_OFF (1): keep the
+                              caller's order.  An instance's results depend on its place
+                              only through the rounding of the back substitution's sums,
+                              whose split over lanes follows the tile size               */
+    int32_t reserved;
 } pf_solve_opts;
 enum { PF_LAUNCH_AUTO = 0, PF_LAUNCH_FUSED = 1, PF_LAUNCH_PHASES = 2 };
+enum { PF_REORDER_AUTO = 0, PF_REORDER_OFF = 1 };
 
 /*
  * pf_analyze -- one-time analysis of a Ybus pattern (Sec. 4.1: pre-order, symbolic LU
@@ -142,7 +154,8 @@ int pf_plan_lu_pattern(pf_plan plan, int32_t *col_ptr, int32_t *row_idx, int32_t
 int pf_plan_schedule(pf_plan plan, int32_t order, int32_t *first, int32_t *width, int32_t *long_rank,
                      int32_t *prev_long);
 
-/* Workspace bytes pf_solve_batch needs for `batch` instances with `opts` (NULL = default). */
+/* Workspace bytes pf_solve_batch needs for `batch` instances with `opts` (NULL = default),
+ * including the per-phase reorder area (16 B per instance and a few KB of counts). */
 size_t pf_workspace_bytes(pf_plan plan, int32_t batch, const pf_solve_opts *opts);
 
 /*

@@ -21,6 +21,7 @@ PF_BUS_PQ, PF_BUS_PV, PF_BUS_REF = 1, 2, 3
 PF_ORDER_NATURAL, PF_ORDER_MIN_DEGREE, PF_ORDER_USER = 0, 1, 2
 PF_FP64, PF_FP32_LU = 0, 1
 PF_LAUNCH_AUTO, PF_LAUNCH_FUSED, PF_LAUNCH_PHASES = 0, 1, 2
+PF_REORDER_AUTO, PF_REORDER_OFF = 0, 1
 PF_ST_CONVERGED, PF_ST_MAXITER, PF_ST_NONFINITE, PF_ST_PIVOT, PF_ST_INTERNAL = 0, 1, 2, 3, -1
 
 EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
@@ -52,7 +53,7 @@ class _PlanInfo(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tile", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("long_slots", ctypes.c_int32), ("launch", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("reorder", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _QueueInfo(ctypes.Structure):
@@ -223,14 +224,15 @@ class Plan:
                "pf_plan_ring")
         return tuple(a[:nl] for a in out)
 
-    def resolve(self, batch: int, precision=PF_FP64, tile=0, waves=0, schedule=0, long_slots=0, launch=0) -> dict:
+    def resolve(self, batch: int, precision=PF_FP64, tile=0, waves=0, schedule=0, long_slots=0, launch=0,
+                reorder=0) -> dict:
         """The configuration a solve of batch instances would use (pf_resolve_opts)."""
         o = _Opts()
         _check(lib().pf_resolve_opts(self._h, int(batch),
-                                     ctypes.byref(_Opts(precision, tile, waves, schedule, long_slots, launch)),
+                                     ctypes.byref(_Opts(precision, tile, waves, schedule, long_slots, launch, reorder)),
                                      ctypes.byref(o)), "pf_resolve_opts")
         return {"precision": o.precision, "tile": o.tile, "waves": o.waves, "schedule": o.schedule,
-                "long_slots": o.long_slots, "launch": o.launch}
+                "long_slots": o.long_slots, "launch": o.launch, "reorder": o.reorder}
 
     def workspace_bytes(self, batch: int, precision=PF_FP64, tile=0, waves=0) -> int:
         o = _Opts(precision, tile, waves)
@@ -303,7 +305,8 @@ def _as_pairs(x, name):
 def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
                 precision: int = PF_FP64, tile: int = 0, waves: int = 0, workspace=None,
                 stream=None, out: Optional[Result] = None, schedule: int = 0,
-                v_fallback=None, long_slots: int = 0, pivot_fallback: bool = False, launch: int = 0) -> Result:
+                v_fallback=None, long_slots: int = 0, pivot_fallback: bool = False, launch: int = 0,
+                reorder: int = 0) -> Result:
     """Run pf_solve_batch on device tensors: ybus complex128 [nnz_y] (or [B][nnz_y]: one set of
     values per instance), sbus complex128 [B][n],
     v0 float64 [B][n][2].  With v_fallback (same shape as v0) pf_solve_batch_warm runs
@@ -323,7 +326,7 @@ def solve_batch(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 1
                      iters=torch.empty(B, dtype=torch.int32, device=v0.device),
                      converged=torch.empty(B, dtype=torch.uint8, device=v0.device),
                      status=torch.empty(B, dtype=torch.int8, device=v0.device))
-    opts = _Opts(precision, tile, waves, schedule, long_slots, launch)
+    opts = _Opts(precision, tile, waves, schedule, long_slots, launch, reorder)
     workspace, wp, avail = _workspace(plan, B, opts, workspace)
     outs = (_vp(out.v.data_ptr()), _vp(out.iters.data_ptr()), _vp(out.converged.data_ptr()),
             _vp(out.status.data_ptr()), _stream_ptr(stream))

@@ -81,7 +81,16 @@ struct KArgs {
     unsigned long long *done_ticks;        // per-instance completion tick (may be null)
     const unsigned long long *t0;          // start tick the completion ticks are relative to
     int sched;                  // 0: level order, 1: elimination order
+    // per-phase launches: the instance held by each slot (tile * T + lane) when the batch has
+    // been reordered; null = slot b holds instance b
+    const int32_t *inst;
+    // a fused launch that resumes a reordered batch: |V| and angle rows and control words
+    // parked after its first update, in instance order
+    const double *vpark;
+    const int4 *cpark;
 };
+
+__device__ __forceinline__ int inst_of(const KArgs &a, int slot) { return a.inst ? a.inst[slot] : slot; }
 
 // Waits until every vector memory load this wavefront has issued has returned (vmcnt(0);
 // the encoding leaves the other counters unconstrained).  The memory counter also counts
@@ -774,8 +783,10 @@ __device__ __forceinline__ void bs_phase(TileCtx<R> &cx, const bool upd_v)
 }
 
 // The whole Newton loop of one tile (T instances) by one workgroup.  Called by the
-// one-tile-per-workgroup kernel and by the persistent multi-pattern queue kernel.
-template <typename R, int T, int NW>
+// one-tile-per-workgroup kernel and by the persistent multi-pattern queue kernel.  With
+// RESUME the tile's slots hold instances a.inst[slot] of a reordered batch, which continue
+// from their parked state (see split_park_kernel).
+template <typename R, int T, int NW, bool RESUME = false>
 __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
 {
     constexpr int SL = 64 / T;          // sub-lanes per instance inside a wavefront
@@ -804,6 +815,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     const int slot = tid / T;
     const int b = tile * T + t;
     const bool valid = b < a.batch;
+    const int bi = RESUME ? (valid ? a.inst[b] : 0) : b;       // the slot's instance
     const int n = P.n;
     const int N = P.N;
 
@@ -835,11 +847,12 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                   done, ldone, err, s_prog, s_piv, s_active, s_reset, nprog, nullptr, N};
 
     // ---- boundary layout [B][n][2] -> tile layout [n][T]
+    const double *vsrc = RESUME ? a.vpark : a.v0;
     for (int i = slot; i < n; i += SLOTS) {
         double vm = 1.0, va = 0.0, ps = 0.0, qs = 0.0;
         if (valid) {
-            const size_t o = ((size_t)b * n + i) * 2;
-            vm = a.v0[o]; va = a.v0[o + 1];
+            const size_t o = ((size_t)bi * n + i) * 2;
+            vm = vsrc[o]; va = vsrc[o + 1];
             ps = a.sbus[o]; qs = a.sbus[o + 1];
         }
         Vm[i * T + t] = vm; Va[i * T + t] = va;
@@ -851,8 +864,22 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         s_iters[t] = 0;
         s_retry[t] = 0; s_reset[t] = 0; s_nupd[t] = 0; s_base[t] = 0;
         s_prevf[t] = INFINITY;
+        if (RESUME && valid) {
+            // {status, iterations, updates, active}, {retried, restart pending, updates when
+            // the attempt began}, {last max |F| (two words), tile error}
+            const int4 c = a.cpark[(size_t)bi * 3], w = a.cpark[(size_t)bi * 3 + 1], x = a.cpark[(size_t)bi * 3 + 2];
+            s_status[t] = c.x; s_iters[t] = c.y; s_nupd[t] = c.z; s_active[t] = c.w;
+            s_retry[t] = w.x; s_reset[t] = w.y; s_base[t] = w.z;
+            s_prevf[t] = __hiloint2double(x.y, x.x);
+        }
     }
-    if (tid == 0) s_err = 0;
+    if (tid == 0) {
+        int e0 = 0;
+        if (RESUME)
+            for (int q = 0; q < T; q++)
+                if (tile * T + q < a.batch) e0 |= a.cpark[(size_t)a.inst[tile * T + q] * 3 + 2].z;
+        s_err = e0;
+    }
     if (tid < NW) s_prog[tid] = 0;
     __syncthreads();
 
@@ -861,7 +888,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         if (a.v_fb) {
             if (s_reset[t] && valid)
                 for (int i = slot; i < n; i += SLOTS) {
-                    const size_t o = ((size_t)b * n + i) * 2;
+                    const size_t o = ((size_t)bi * n + i) * 2;
                     Vm[i * T + t] = a.v_fb[o];
                     Va[i * T + t] = a.v_fb[o + 1];
                 }
@@ -883,7 +910,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         // |V_i| conj Y_ii.  P rows take the real part, Q rows the imaginary part.
         const bool build = a.mode != MODE_MISMATCH;
         // this instance's Ybus values (padding lanes of the last tile read instance 0's)
-        const double2 *yrow = reinterpret_cast<const double2 *>(a.ybus + (valid ? (size_t)b * a.ybus_stride : 0));
+        const double2 *yrow = reinterpret_cast<const double2 *>(a.ybus + (valid ? (size_t)bi * a.ybus_stride : 0));
         double mx = 0.0;
         int bad = 0;
         for (int i = slot; i < n; i += SLOTS) {
@@ -1025,16 +1052,16 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     // ---- tile layout -> boundary layout
     if (valid) {
         for (int i = slot; i < n; i += SLOTS) {
-            const size_t o = ((size_t)b * n + i) * 2;
+            const size_t o = ((size_t)bi * n + i) * 2;
             a.v_out[o] = Vm[i * T + t];
             a.v_out[o + 1] = Va[i * T + t];
         }
         if (s == 0 && wave == 0) {
-            if (a.done_ticks) a.done_ticks[b] = wall_clock64() - *a.t0;
+            if (a.done_ticks) a.done_ticks[bi] = wall_clock64() - *a.t0;
             const int st = s_err ? PF_ST_INTERNAL : s_status[t];
-            a.iters_out[b] = s_iters[t];
-            a.conv_out[b] = st == PF_ST_CONVERGED ? 1 : 0;
-            if (a.status_out) a.status_out[b] = (int8_t)st;
+            a.iters_out[bi] = s_iters[t];
+            a.conv_out[bi] = st == PF_ST_CONVERGED ? 1 : 0;
+            if (a.status_out) a.status_out[bi] = (int8_t)st;
         }
     }
 }
@@ -1045,6 +1072,14 @@ template <typename R, int T, int NW>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void nr_tile_kernel(KArgs a)
 {
     nr_tile_body<R, T, NW>(a, blockIdx.x);
+}
+
+// The head of a reordered batch: its hardest instances finish their Newton iterations in one
+// launch whose workgroups keep their CUs until done, at one tile's latency per iteration.
+template <typename R, int T, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void nr_head_kernel(KArgs a)
+{
+    nr_tile_body<R, T, NW, true>(a, blockIdx.x);
 }
 
 // Persistent launch over a queue of work items (one per pattern / batch): workgroups pop
@@ -1116,36 +1151,131 @@ __device__ __forceinline__ double *tile_prevf(const KArgs &a, int tile)
     return reinterpret_cast<double *>(tile_ctl<T>(a, tile) + 2 * T + 1);
 }
 
-// boundary layout [B][n][2] -> tile layout; instance states and tile flags initialised
+// Boundary rows [B][n][2] <-> tile layout [n][T], through LDS: each round moves kMBlock / T
+// buses of the tile's T instances, reading (or writing) every instance's row segment
+// contiguously and the tile layout contiguously.  Slot b's row is its instance's.
 template <int T>
-__global__ __launch_bounds__(kMBlock) void split_in_kernel(KArgs a)
+struct RowStage {
+    static constexpr int CH = kMBlock / T;
+    double v[2][2 * CH][T + 1];
+};
+
+// layout in: |V| and angle from vsrc (the start v0, or the rows parked after the first
+// update), the P and Q set points from sbus; instance states either initialised or, with
+// csrc, taken from the parked control words (see split_park_kernel)
+template <int T>
+__global__ __launch_bounds__(kMBlock) void split_in_kernel(KArgs a, const double *vsrc, const int4 *csrc)
 {
-    const int tile = blockIdx.x, tid = threadIdx.x, t = tid % T;
-    const int b = tile * T + t;
-    const bool valid = b < a.batch;
+    constexpr int CH = RowStage<T>::CH;
+    __shared__ RowStage<T> st;
+    __shared__ int s_row[T];
+    const int tile = blockIdx.x, tid = threadIdx.x;
     const int n = a.p.n;
+    if (tid < T) {
+        const int b = tile * T + tid;
+        s_row[tid] = b < a.batch ? inst_of(a, b) : -1;
+    }
+    __syncthreads();
     double *vec = reinterpret_cast<double *>(a.ws + (size_t)tile * a.tile_bytes + a.off_vec);
     const size_t nT = (size_t)n * T;
-    for (int i = tid / T; i < n; i += kMBlock / T) {
-        double vm = 1.0, va = 0.0, ps = 0.0, qs = 0.0;
-        if (valid) {
-            const size_t o = ((size_t)b * n + i) * 2;
-            vm = a.v0[o]; va = a.v0[o + 1];
-            ps = a.sbus[o]; qs = a.sbus[o + 1];
+    for (int i0 = 0; i0 < n; i0 += CH) {
+        const int nb = min(CH, n - i0);
+        for (int e = tid; e < T * 2 * CH; e += kMBlock) {
+            const int t = e / (2 * CH), w = e - t * (2 * CH);      // w = 2 * bus + (0 |V| or P, 1 angle or Q)
+            const int row = s_row[t];
+            double v = (w & 1) ? 0.0 : 1.0, sp = 0.0;
+            if (row >= 0 && w < 2 * nb) {
+                const size_t o = ((size_t)row * n + i0) * 2 + w;
+                v = vsrc[o];
+                sp = a.sbus[o];
+            }
+            st.v[0][w][t] = v;
+            st.v[1][w][t] = sp;
         }
-        vec[i * T + t] = vm; vec[nT + i * T + t] = va;
-        vec[2 * nT + i * T + t] = ps; vec[3 * nT + i * T + t] = qs;
+        __syncthreads();
+        for (int e = tid; e < nb * T; e += kMBlock) {
+            const int il = e / T, t = e - il * T;
+            const size_t o = (size_t)(i0 + il) * T + t;
+            vec[o] = st.v[0][2 * il][t];
+            vec[nT + o] = st.v[0][2 * il + 1][t];
+            vec[2 * nT + o] = st.v[1][2 * il][t];
+            vec[3 * nT + o] = st.v[1][2 * il + 1][t];
+        }
+        __syncthreads();
     }
     int4 *ctl = tile_ctl<T>(a, tile);
+    __shared__ int s_act[T], s_err[T];
     if (tid < T) {
-        ctl[t] = make_int4(PF_ST_MAXITER, 0, 0, valid ? 1 : 0);
-        tile_warm<T>(a, tile)[t] = make_int4(0, 0, 0, 0);
-        tile_prevf<T>(a, tile)[t] = INFINITY;
+        const int row = s_row[tid];
+        int4 c = make_int4(PF_ST_MAXITER, 0, 0, row >= 0 ? 1 : 0), w = make_int4(0, 0, 0, 0);
+        double pfv = INFINITY;
+        int er = 0;
+        if (csrc && row >= 0) {
+            c = csrc[(size_t)row * 3];
+            w = csrc[(size_t)row * 3 + 1];
+            const int4 x = csrc[(size_t)row * 3 + 2];
+            pfv = __hiloint2double(x.y, x.x);
+            er = x.z;
+        } else if (csrc) {
+            c.w = 0;
+        }
+        ctl[tid] = c;
+        tile_warm<T>(a, tile)[tid] = w;
+        tile_prevf<T>(a, tile)[tid] = pfv;
+        s_act[tid] = c.w;
+        s_err[tid] = er;
     }
+    __syncthreads();
     if (tid == 0) {
+        int any = 0, err = 0;
+        for (int q = 0; q < T; q++) { any |= s_act[q]; err |= s_err[q]; }
         int *tf = reinterpret_cast<int *>(ctl + T);
-        tf[0] = tile * T < a.batch ? 1 : 0;
-        tf[1] = 0;
+        tf[0] = any;
+        tf[1] = err;
+    }
+}
+
+// After the first update of a batch that is then reordered: every slot's |V| and angle go
+// to row inst_of(slot) of park ([B][n][2]) and its control words (state, fallback state,
+// last max |F| and the tile's internal-error flag) to ctl_park[3 row ...].
+template <int T>
+__global__ __launch_bounds__(kMBlock) void split_park_kernel(KArgs a, double *park, int4 *ctl_park)
+{
+    constexpr int CH = RowStage<T>::CH;
+    __shared__ RowStage<T> st;
+    __shared__ int s_row[T];
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int n = a.p.n;
+    if (tid < T) {
+        const int b = tile * T + tid;
+        s_row[tid] = b < a.batch ? inst_of(a, b) : -1;
+    }
+    __syncthreads();
+    const double *vec = reinterpret_cast<const double *>(a.ws + (size_t)tile * a.tile_bytes + a.off_vec);
+    const size_t nT = (size_t)n * T;
+    for (int i0 = 0; i0 < n; i0 += CH) {
+        const int nb = min(CH, n - i0);
+        for (int e = tid; e < nb * T; e += kMBlock) {
+            const int il = e / T, t = e - il * T;
+            const size_t o = (size_t)(i0 + il) * T + t;
+            st.v[0][2 * il][t] = vec[o];
+            st.v[0][2 * il + 1][t] = vec[nT + o];
+        }
+        __syncthreads();
+        for (int e = tid; e < T * 2 * CH; e += kMBlock) {
+            const int t = e / (2 * CH), w = e - t * (2 * CH);
+            const int row = s_row[t];
+            if (row >= 0 && w < 2 * nb) park[((size_t)row * n + i0) * 2 + w] = st.v[0][w][t];
+        }
+        __syncthreads();
+    }
+    if (tid < T && s_row[tid] >= 0) {
+        const int4 *ctl = tile_ctl<T>(a, tile);
+        const size_t r = (size_t)s_row[tid] * 3;
+        ctl_park[r] = ctl[tid];
+        ctl_park[r + 1] = tile_warm<T>(a, tile)[tid];
+        const double pfv = tile_prevf<T>(a, tile)[tid];
+        ctl_park[r + 2] = make_int4(__double2loint(pfv), __double2hiint(pfv), reinterpret_cast<const int *>(ctl + T)[1], 0);
     }
 }
 
@@ -1170,7 +1300,7 @@ __global__ __launch_bounds__(kMBlock) void split_v_kernel(KArgs a, int ntiles)
         // an instance whose first attempt failed restarts from the fallback point
         const int b = tile * T + t;
         if (a.v_fb && b < a.batch && tile_warm<T>(a, tile)[t].y) {
-            const size_t o = ((size_t)b * n + i) * 2;
+            const size_t o = ((size_t)inst_of(a, b) * n + i) * 2;
             vec[i * T + t] = a.v_fb[o];
             vec[nT + i * T + t] = a.v_fb[o + 1];
         }
@@ -1207,7 +1337,8 @@ __global__ __launch_bounds__(kMBlock) void split_m_kernel(KArgs a, int ntiles, i
         const double2 *Vc = reinterpret_cast<const double2 *>(vec + 4 * nT);
         const int b = tile * T + t;
         const bool valid = b < a.batch;
-        const double2 *yrow = reinterpret_cast<const double2 *>(a.ybus + (valid ? (size_t)b * a.ybus_stride : 0));
+        const double2 *yrow = reinterpret_cast<const double2 *>(
+            a.ybus + (valid && a.ybus_stride ? (size_t)inst_of(a, b) * a.ybus_stride : 0));
         const int i = blk * BUSB + ib;
         double mx = 0.0;
         int bad = 0;
@@ -1437,27 +1568,158 @@ __global__ __launch_bounds__(kMBlock) void split_out_kernel(KArgs a)
         }
     }
     __syncthreads();
-    if (!valid) return;
+    constexpr int CH = RowStage<T>::CH;
+    __shared__ RowStage<T> st;
+    __shared__ int s_row[T];
+    if (tid < T) s_row[tid] = valid ? inst_of(a, b) : -1;
+    __syncthreads();
     const int n = a.p.n;
     const double *vec = reinterpret_cast<const double *>(a.ws + (size_t)tile * a.tile_bytes + a.off_vec);
     const size_t nT = (size_t)n * T;
-    for (int i = tid / T; i < n; i += kMBlock / T) {
-        const size_t o = ((size_t)b * n + i) * 2;
-        a.v_out[o] = vec[i * T + t];
-        a.v_out[o + 1] = vec[nT + i * T + t];
+    for (int i0 = 0; i0 < n; i0 += CH) {
+        const int nb = min(CH, n - i0);
+        for (int e = tid; e < nb * T; e += kMBlock) {
+            const int il = e / T, tt = e - il * T;
+            const size_t o = (size_t)(i0 + il) * T + tt;
+            st.v[0][2 * il][tt] = vec[o];
+            st.v[0][2 * il + 1][tt] = vec[nT + o];
+        }
+        __syncthreads();
+        for (int e = tid; e < T * 2 * CH; e += kMBlock) {
+            const int tt = e / (2 * CH), w = e - tt * (2 * CH);
+            const int row = s_row[tt];
+            if (row >= 0 && w < 2 * nb) a.v_out[((size_t)row * n + i0) * 2 + w] = st.v[0][w][tt];
+        }
+        __syncthreads();
     }
-    if (tid < T) {
+    if (tid < T && valid) {
+        const int bi = s_row[t];
         const int4 c = ctl[t];
-        const int st = tf[1] ? PF_ST_INTERNAL : c.x;
-        a.iters_out[b] = c.y;
-        a.conv_out[b] = st == PF_ST_CONVERGED ? 1 : 0;
-        if (a.status_out) a.status_out[b] = (int8_t)st;
+        const int st_ = tf[1] ? PF_ST_INTERNAL : c.x;
+        a.iters_out[bi] = c.y;
+        a.conv_out[bi] = st_ == PF_ST_CONVERGED ? 1 : 0;
+        if (a.status_out) a.status_out[bi] = (int8_t)st_;
+    }
+}
+
+// ---- hardest-first reordering of a batch after its first update (per-phase launches)
+// The instances that need the most Newton iterations are those whose first step was the
+// largest.  Placing them in the first tiles gives the later iterations dense tiles (a tile
+// runs until its slowest instance stops) and starts their long iteration chains first, so
+// those overlap the rest of the batch instead of extending its end.
+
+// Sort key of each slot after the first update: 16 bits of max |dx| (the float's sign,
+// exponent and leading mantissa bits, monotone for non-negative values), stored inverted
+// so that an ascending sort puts the largest steps first.  A slot whose instance has
+// stopped gets the smallest key, one that restarts from its fallback point the largest
+// (a fresh solve lies ahead of it).  ids[b] = b.
+template <typename R, int T>
+__global__ __launch_bounds__(kMBlock) void split_key_kernel(KArgs a, uint32_t *keys, int32_t *ids)
+{
+    __shared__ float s_mx[kMBlock];
+    const int tile = blockIdx.x, tid = threadIdx.x, t = tid % T;
+    const int b = tile * T + t;
+    const int4 *ctl = tile_ctl<T>(a, tile);
+    const R *Yv = reinterpret_cast<const R *>(a.ws + (size_t)tile * a.tile_bytes + a.off_y);
+    float mx = 0.f;
+    for (int j = tid / T; j < a.p.N; j += kMBlock / T) {
+        const float z = fabsf((float)Yv[j * T + t]);
+        mx = (z > mx || z != z) ? z : mx;                 // NaN wins
+    }
+    s_mx[tid] = mx;
+    __syncthreads();
+    if (tid < T && b < a.batch) {
+        float m = 0.f;
+        for (int x = 0; x < kMBlock / T; x++) {
+            const float z = s_mx[x * T + t];
+            m = (z > m || z != z) ? z : m;
+        }
+        uint32_t bits;
+        if (!ctl[t].w) bits = 0;
+        else if (tile_warm<T>(a, tile)[t].y || m != m) bits = 0xFFFFu;
+        else bits = __float_as_uint(m) >> 16;             // m >= 0: at most 0x7F80 (inf)
+        keys[b] = 0xFFFFu - bits;
+        ids[b] = b;
+    }
+}
+
+// One pass of a stable least-significant-digit radix sort over 8 bits of 16-bit keys:
+// per block of kSortSeg items a digit histogram, an exclusive scan over (digit, block),
+// then a stable scatter.
+constexpr int kSortSeg = 1024;
+
+__global__ __launch_bounds__(256) void sort_hist_kernel(const uint32_t *keys, int n, int shift, int32_t *hist)
+{
+    __shared__ int cnt[256];
+    const int tid = threadIdx.x, blk = blockIdx.x, nblk = gridDim.x;
+    cnt[tid] = 0;
+    __syncthreads();
+    for (int r = 0; r < kSortSeg / 256; r++) {
+        const int p = blk * kSortSeg + r * 256 + tid;
+        if (p < n) atomicAdd(&cnt[(keys[p] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    hist[(size_t)tid * nblk + blk] = cnt[tid];
+}
+
+// exclusive scan of m counts in place by one workgroup
+__global__ __launch_bounds__(1024) void sort_scan_kernel(int32_t *hist, int m)
+{
+    __shared__ int part[1024];
+    const int tid = threadIdx.x;
+    const int per = (m + 1023) / 1024;
+    const int lo = min(m, tid * per), hi = min(m, lo + per);
+    int s = 0;
+    for (int i = lo; i < hi; i++) s += hist[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = part[tid] - s;
+    for (int i = lo; i < hi; i++) {
+        const int c = hist[i];
+        hist[i] = run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(256) void sort_scatter_kernel(const uint32_t *kin, const int32_t *iin, uint32_t *kout,
+                                                           int32_t *iout, int n, int shift, const int32_t *hist)
+{
+    __shared__ int dig[256];
+    __shared__ int base[256];
+    const int tid = threadIdx.x, blk = blockIdx.x, nblk = gridDim.x;
+    base[tid] = 0;
+    __syncthreads();
+    for (int r = 0; r < kSortSeg / 256; r++) {
+        const int p = blk * kSortSeg + r * 256 + tid;
+        const bool ok = p < n;
+        const uint32_t k = ok ? kin[p] : 0u;
+        const int d = ok ? (int)((k >> shift) & 255) : 256;
+        dig[tid] = d;
+        __syncthreads();
+        if (ok) {
+            int rank = 0;
+            for (int j = 0; j < tid; j++) rank += dig[j] == d;
+            const int pos = hist[(size_t)d * nblk + blk] + base[d] + rank;
+            kout[pos] = k;
+            iout[pos] = iin[p];
+        }
+        __syncthreads();
+        int c = 0;
+        for (int j = 0; j < 256; j++) c += dig[j] == tid;
+        base[tid] += c;
+        __syncthreads();
     }
 }
 
 // ------------------------------------------------------------------ launch configuration
 struct Config {
-    int precision, tile, waves, schedule, n_long, launch;
+    int precision, tile, waves, schedule, n_long, launch, reorder;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1513,6 +1775,8 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
     c.schedule = o ? o->schedule : 0;
     c.launch = o ? o->launch : PF_LAUNCH_AUTO;
     if (c.launch < PF_LAUNCH_AUTO || c.launch > PF_LAUNCH_PHASES) { err = "launch must be 0, 1 or 2"; return false; }
+    c.reorder = o ? o->reorder : PF_REORDER_AUTO;
+    if (c.reorder != PF_REORDER_AUTO && c.reorder != PF_REORDER_OFF) { err = "reorder must be 0 or 1"; return false; }
     if (c.schedule != 0 && c.schedule != 1) { err = "schedule must be 0 or 1"; return false; }
     const int long_slots = o ? o->long_slots : 0;
     if (long_slots < 0 || long_slots > kMaxLong) {
@@ -1652,9 +1916,15 @@ static hipError_t launch(const Config &c, const KArgs &a, int grid, size_t lds, 
 
 // The per-phase launches of one solve: layout in, then per iteration the mismatch and
 // Jacobian, the refactorization (with the convergence decision first) and the back
-// substitution, then the final mismatch, decision and layout out.
+// substitution, then the final mismatch, decision and layout out.  A part of the sequence:
+// with head the layout in, iterations [it0, it1), with tail the final pass and layout out.
+// With a fallback start, the attempts' updates and the restart's decision take at most
+// 2 max_iter + 1 iterations.
+static int phase_iterations(const KArgs &a) { return a.v_fb ? 2 * a.max_iter + 1 : a.max_iter; }
+
 template <typename R, int T, int NW>
-static hipError_t launch_phases_t(const KArgs &a, int ntiles, size_t lds, hipStream_t st)
+static hipError_t launch_phases_t(const KArgs &a, int ntiles, size_t lds, hipStream_t st, bool head, int it0, int it1,
+                                  bool tail, const double *vsrc, const int4 *csrc)
 {
     auto lu = split_lu_kernel<R, T, NW>;
     auto bs = split_bs_kernel<R, T, NW>;
@@ -1663,32 +1933,66 @@ static hipError_t launch_phases_t(const KArgs &a, int ntiles, size_t lds, hipStr
     if (e == hipSuccess) e = allow_lds(bs, bs_lds);
     if (e != hipSuccess) return e;
     const int mgrid = std::max(1, std::min(ntiles * a.nbb, 4096));
-    hipLaunchKernelGGL(split_in_kernel<T>, dim3(ntiles), dim3(kMBlock), 0, st, a);
-    // with a fallback start, the attempts' updates and the restart's decision take at most
-    // 2 max_iter + 1 iterations
-    const int iters = a.v_fb ? 2 * a.max_iter + 1 : a.max_iter;
-    for (int k = 0; k < iters; k++) {
+    if (head) hipLaunchKernelGGL(split_in_kernel<T>, dim3(ntiles), dim3(kMBlock), 0, st, a, vsrc ? vsrc : a.v0, csrc);
+    for (int k = it0; k < it1; k++) {
         hipLaunchKernelGGL(split_v_kernel<T>, dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles);
         hipLaunchKernelGGL((split_m_kernel<R, T>), dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles, 1);
         hipLaunchKernelGGL(lu, dim3(ntiles), dim3(NW * 64), lds, st, a);
         hipLaunchKernelGGL(bs, dim3(ntiles), dim3(NW * 64), bs_lds, st, a);
     }
-    hipLaunchKernelGGL(split_v_kernel<T>, dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles);
-    hipLaunchKernelGGL((split_m_kernel<R, T>), dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles, 0);
-    hipLaunchKernelGGL(split_out_kernel<T>, dim3(ntiles), dim3(kMBlock), 0, st, a);
+    if (tail) {
+        hipLaunchKernelGGL(split_v_kernel<T>, dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles);
+        hipLaunchKernelGGL((split_m_kernel<R, T>), dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles, 0);
+        hipLaunchKernelGGL(split_out_kernel<T>, dim3(ntiles), dim3(kMBlock), 0, st, a);
+    }
     return hipGetLastError();
 }
 
-#define PF_DISPATCH_PHASES_NW(R, T)                                            \
-    switch (c.waves) {                                                         \
-    case 2: return launch_phases_t<R, T, 2>(a, grid, lds, st);                 \
-    case 4: return launch_phases_t<R, T, 4>(a, grid, lds, st);                 \
-    case 16: return launch_phases_t<R, T, 16>(a, grid, lds, st);               \
-    default: return launch_phases_t<R, T, 8>(a, grid, lds, st);                \
+// Reorders a batch hardest first after its first update (see split_key_kernel): the sort
+// key per slot and two radix passes (ids0 receives the sorted slots, which are the
+// instances), and every instance's |V|, angle and control words parked in instance order.
+template <typename R, int T>
+static hipError_t launch_reorder_t(const KArgs &a, int ntiles, hipStream_t st, uint32_t *keys0, int32_t *ids0,
+                                   uint32_t *keys1, int32_t *ids1, int32_t *hist, double *park, int4 *ctl_park)
+{
+    const int n = a.batch, nblk = (n + kSortSeg - 1) / kSortSeg;
+    hipLaunchKernelGGL((split_key_kernel<R, T>), dim3(ntiles), dim3(kMBlock), 0, st, a, keys0, ids0);
+    for (int pass = 0; pass < 2; pass++) {
+        const uint32_t *ki = pass ? keys1 : keys0;
+        const int32_t *ii = pass ? ids1 : ids0;
+        uint32_t *ko = pass ? keys0 : keys1;
+        int32_t *io = pass ? ids0 : ids1;
+        hipLaunchKernelGGL(sort_hist_kernel, dim3(nblk), dim3(256), 0, st, ki, n, 8 * pass, hist);
+        hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(1024), 0, st, hist, 256 * nblk);
+        hipLaunchKernelGGL(sort_scatter_kernel, dim3(nblk), dim3(256), 0, st, ki, ii, ko, io, n, 8 * pass, hist);
+    }
+    hipLaunchKernelGGL(split_park_kernel<T>, dim3(ntiles), dim3(kMBlock), 0, st, a, park, ctl_park);
+    return hipGetLastError();
+}
+
+// workgroups of the refactorization kernel that fit on one CU (registers, LDS, waves)
+template <typename R, int T, int NW>
+static hipError_t lu_residency_t(size_t lds, int *nb)
+{
+    auto lu = split_lu_kernel<R, T, NW>;
+    hipError_t e = allow_lds(lu, lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lu, NW * 64, lds);
+}
+
+#define PF_DISPATCH_PHASES_NW(R, T)                                                                     \
+    switch (c.waves) {                                                                                  \
+    case 2: return launch_phases_t<R, T, 2>(a, grid, lds, st, head, it0, it1, tail, vsrc, csrc);        \
+    case 4: return launch_phases_t<R, T, 4>(a, grid, lds, st, head, it0, it1, tail, vsrc, csrc);        \
+    case 16: return launch_phases_t<R, T, 16>(a, grid, lds, st, head, it0, it1, tail, vsrc, csrc);      \
+    default: return launch_phases_t<R, T, 8>(a, grid, lds, st, head, it0, it1, tail, vsrc, csrc);       \
     }
 
-static hipError_t launch_phases(const Config &c, const KArgs &a, int grid, size_t lds, hipStream_t st)
+static hipError_t launch_phases(const Config &c, const KArgs &a, int grid, size_t lds, hipStream_t st,
+                                bool head = true, int it0 = 0, int it1 = -1, bool tail = true,
+                                const double *vsrc = nullptr, const int4 *csrc = nullptr)
 {
+    if (it1 < 0) it1 = phase_iterations(a);
     if (c.precision == PF_FP64) {
         if (c.tile == 4) { PF_DISPATCH_PHASES_NW(double, 4) }
         if (c.tile == 8) { PF_DISPATCH_PHASES_NW(double, 8) }
@@ -1698,6 +2002,40 @@ static hipError_t launch_phases(const Config &c, const KArgs &a, int grid, size_
         if (c.tile == 16) { PF_DISPATCH_PHASES_NW(float, 16) }
         PF_DISPATCH_PHASES_NW(float, 32)
     }
+}
+
+#define PF_DISPATCH_RESIDENCY_NW(R, T)                                         \
+    switch (c.waves) {                                                         \
+    case 2: return lu_residency_t<R, T, 2>(lds, nb);                           \
+    case 4: return lu_residency_t<R, T, 4>(lds, nb);                           \
+    case 16: return lu_residency_t<R, T, 16>(lds, nb);                         \
+    default: return lu_residency_t<R, T, 8>(lds, nb);                          \
+    }
+
+static hipError_t lu_residency(const Config &c, size_t lds, int *nb)
+{
+    if (c.precision == PF_FP64) {
+        if (c.tile == 4) { PF_DISPATCH_RESIDENCY_NW(double, 4) }
+        if (c.tile == 8) { PF_DISPATCH_RESIDENCY_NW(double, 8) }
+        PF_DISPATCH_RESIDENCY_NW(double, 16)
+    } else {
+        if (c.tile == 8) { PF_DISPATCH_RESIDENCY_NW(float, 8) }
+        if (c.tile == 16) { PF_DISPATCH_RESIDENCY_NW(float, 16) }
+        PF_DISPATCH_RESIDENCY_NW(float, 32)
+    }
+}
+
+static hipError_t launch_reorder(const Config &c, const KArgs &a, int ntiles, hipStream_t st, uint32_t *k0,
+                                 int32_t *i0, uint32_t *k1, int32_t *i1, int32_t *hist, double *park, int4 *cp)
+{
+    if (c.precision == PF_FP64) {
+        if (c.tile == 4) return launch_reorder_t<double, 4>(a, ntiles, st, k0, i0, k1, i1, hist, park, cp);
+        if (c.tile == 8) return launch_reorder_t<double, 8>(a, ntiles, st, k0, i0, k1, i1, hist, park, cp);
+        return launch_reorder_t<double, 16>(a, ntiles, st, k0, i0, k1, i1, hist, park, cp);
+    }
+    if (c.tile == 8) return launch_reorder_t<float, 8>(a, ntiles, st, k0, i0, k1, i1, hist, park, cp);
+    if (c.tile == 16) return launch_reorder_t<float, 16>(a, ntiles, st, k0, i0, k1, i1, hist, park, cp);
+    return launch_reorder_t<float, 32>(a, ntiles, st, k0, i0, k1, i1, hist, park, cp);
 }
 
 static int upload(Plan *pl);
@@ -1759,13 +2097,17 @@ static int make_args(Plan *pl, const Config &c, int32_t batch, const double *ybu
 }
 
 // Per-phase launches over a batch of several generations of tiles: the batch is cut into
-// chunks of one generation each, and the chunks' launch sequences go to a small pool of
-// streams (default priority) that start after the caller's stream and that the caller's
-// stream waits for.  A chunk whose instances need many iterations then overlaps the
-// other chunks' work instead of running alone after them.  The pool and its events are
-// created once per device and kept; `pooled` = false (the allocation-free entry point)
-// keeps everything on the caller's stream.
-constexpr int kPhaseStreams = 4;
+// chunks of one generation each (the tiles whose refactorization workgroups fit on the
+// device at once), and the chunks' launch sequences go to four workers: the caller's
+// stream and three pool streams (default priority) that start after it and that it waits
+// for.  A chunk whose instances need many iterations then overlaps the other chunks' work
+// instead of running alone after them.  When the workspace holds the reorder area, the
+// first update runs over the whole batch on the caller's stream, the batch is reordered
+// hardest first, and the first chunk (the hardest instances) gets the caller's stream to
+// itself.  The pool and its events are created once per device and kept; `pooled` = false
+// (the allocation-free entry point) keeps everything on the caller's stream.
+constexpr int kPhaseStreams = 3;
+constexpr int kHeadTiles = 32;
 struct PhasePool {
     hipStream_t st[kPhaseStreams] = {};
     hipEvent_t start = nullptr, fin[kPhaseStreams] = {};
@@ -1775,8 +2117,50 @@ struct PhasePool {
 static std::mutex g_pool_mu;
 static PhasePool g_pool[64];
 
-static hipError_t launch_phases_chunked(const Config &c, const KArgs &a, int ntiles, size_t lds, hipStream_t user,
-                                        bool pooled)
+// The head of a reordered batch runs the fused kernel in its lowest-latency form: the
+// smallest tile of the precision, sixteen wavefronts, and as many long slots as fit.
+static bool head_config(const HostPlan &h, const Config &c, Config &ch)
+{
+    ch = c;
+    ch.tile = c.precision == PF_FP64 ? 4 : 8;
+    ch.waves = 16;
+    ch.launch = PF_LAUNCH_FUSED;
+    const int lo = h.n_longp > 0 ? 1 : 0;
+    for (ch.n_long = std::min(kMaxLong, h.n_longp); ch.n_long >= lo; ch.n_long--)
+        if (lds_bytes(h, ch) <= kLdsLimit) return true;
+    return false;
+}
+
+// bytes after the tiles' blocks that the reorder needs: two key and two slot arrays of batch
+// words, the radix sort's (digit, block) counts, the parked |V| and angle rows
+// ([batch][n][2]) and control words (three int4 per instance), and the head's tiles
+static size_t order_bytes(const HostPlan &h, const Config &c, int64_t batch)
+{
+    const size_t nblk = (size_t)((batch + kSortSeg - 1) / kSortSeg);
+    size_t bytes = 4 * align256((size_t)batch * 4) + align256(nblk * 256 * 4) + align256((size_t)batch * h.n * 16) +
+                   align256((size_t)batch * 48);
+    Config ch;
+    if (head_config(h, c, ch)) bytes += (size_t)kHeadTiles * tile_layout(h, ch).bytes;
+    return bytes;
+}
+
+#define PF_HEAD_LAUNCH(R, TH)                                                                 \
+    {                                                                                         \
+        auto fn = nr_head_kernel<R, TH, 16>;                                                  \
+        hipError_t e = allow_lds(fn, lds);                                                    \
+        if (e != hipSuccess) return e;                                                        \
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(16 * 64), lds, st, ah);                       \
+        return hipGetLastError();                                                             \
+    }
+
+static hipError_t launch_head(const Config &ch, const KArgs &ah, int grid, size_t lds, hipStream_t st)
+{
+    if (ch.precision == PF_FP64) PF_HEAD_LAUNCH(double, 4)
+    PF_HEAD_LAUNCH(float, 8)
+}
+
+static hipError_t launch_phases_chunked(const HostPlan &h, const Config &c, const KArgs &a, int ntiles, size_t lds,
+                                        hipStream_t user, bool pooled, bool reorder)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1793,34 +2177,101 @@ static hipError_t launch_phases_chunked(const Config &c, const KArgs &a, int nti
         if ((e = hipEventCreateWithFlags(&pp.start, hipEventDisableTiming)) != hipSuccess) return e;
         pp.ready = true;
     }
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(kLdsLimit / std::max<size_t>(lds, 1), 16 / c.waves));
-    const int gen = std::max(1, pp.cus * per_cu);
+    int per_cu = 0;
+    if ((e = lu_residency(c, lds, &per_cu)) != hipSuccess) return e;
+    const int gen = std::max(1, pp.cus * std::max(1, per_cu));
     const int nchunk = (ntiles + gen - 1) / gen;
     if (nchunk <= 1) return launch_phases(c, a, ntiles, lds, user);
-    const int ns = std::min(nchunk, kPhaseStreams);
+    const int iters = phase_iterations(a);
+    const int32_t *order = nullptr;
+    double *park = nullptr;
+    int4 *ctl_park = nullptr;
+    Config ch;
+    const bool head = reorder && head_config(h, c, ch);
+    char *head_ws = nullptr;
+    if (reorder && iters > 1) {
+        char *ob = a.ws + (size_t)ntiles * a.tile_bytes;
+        const size_t w = align256((size_t)a.batch * 4);
+        uint32_t *k0 = reinterpret_cast<uint32_t *>(ob);
+        int32_t *i0 = reinterpret_cast<int32_t *>(ob + w);
+        uint32_t *k1 = reinterpret_cast<uint32_t *>(ob + 2 * w);
+        int32_t *i1 = reinterpret_cast<int32_t *>(ob + 3 * w);
+        int32_t *hist = reinterpret_cast<int32_t *>(ob + 4 * w);
+        const size_t nblk = (size_t)((a.batch + kSortSeg - 1) / kSortSeg);
+        park = reinterpret_cast<double *>(ob + 4 * w + align256(nblk * 256 * 4));
+        ctl_park = reinterpret_cast<int4 *>(reinterpret_cast<char *>(park) + align256((size_t)a.batch * a.p.n * 16));
+        head_ws = reinterpret_cast<char *>(ctl_park) + align256((size_t)a.batch * 48);
+        if ((e = launch_phases(c, a, ntiles, lds, user, true, 0, 1, false)) != hipSuccess) return e;
+        if ((e = launch_reorder(c, a, ntiles, user, k0, i0, k1, i1, hist, park, ctl_park)) != hipSuccess) return e;
+        order = i0;
+    }
+    // With the reorder, the head (the hardest instances: kHeadTiles tiles of the head
+    // configuration) runs as one fused launch on the caller's stream: its workgroups hold
+    // their CUs until their long iteration chains end, at one tile's latency per iteration.
+    // The other instances follow in one-generation chunks of per-phase launches on the pool's
+    // streams (on every worker without the reorder).
+    // the pool's streams start after the reorder, not after the head
     if ((e = hipEventRecord(pp.start, user)) != hipSuccess) return e;
-    for (int i = 0; i < ns; i++)
-        if ((e = hipStreamWaitEvent(pp.st[i], pp.start, 0)) != hipSuccess) return e;
+    int hcount = 0;
+    if (order && head) {
+        const TileLayout Lh = tile_layout(h, ch);
+        hcount = std::min(a.batch, kHeadTiles * ch.tile);
+        KArgs ah = a;
+        ah.ws = head_ws;
+        ah.tile_bytes = Lh.bytes; ah.off_y = Lh.off_y; ah.off_vec = Lh.off_vec;
+        ah.off_ctl = Lh.off_ctl; ah.off_part = Lh.off_part; ah.nbb = Lh.nbb;
+        ah.n_long = ch.n_long;
+        ah.batch = hcount;
+        ah.inst = order;
+        ah.vpark = park;
+        ah.cpark = ctl_park;
+        if ((e = launch_head(ch, ah, (hcount + ch.tile - 1) / ch.tile, lds_bytes(h, ch), user)) != hipSuccess) return e;
+    }
+    const int btiles = (a.batch - hcount + c.tile - 1) / c.tile;
+    // the head's workgroups hold their CUs throughout: a generation of the others fits the rest
+    const int hgrid = (hcount + (head ? ch.tile : 1) - 1) / (head ? ch.tile : 1);
+    const int bgen = hcount > 0 ? std::max(1, (pp.cus - std::min(hgrid, pp.cus / 2)) * std::max(1, per_cu)) : gen;
+    std::vector<int> cut{0};
+    if (order && !head) cut.push_back(std::min(btiles, kHeadTiles));
+    while (cut.back() < btiles) cut.push_back(std::min(btiles, cut.back() + bgen));
+    const int nparts = (int)cut.size() - 1;
+    // workers: 0 = the caller's stream, then the pool's streams; with a fused head the
+    // caller's stream holds only the head
+    hipStream_t wk[kPhaseStreams + 1] = {user, pp.st[0], pp.st[1], pp.st[2]};
+    const int w0 = hcount > 0 ? 1 : 0;
+    const int nw = std::min(nparts + w0, kPhaseStreams + 1);
+    for (int i = 1; i < nw; i++)
+        if ((e = hipStreamWaitEvent(wk[i], pp.start, 0)) != hipSuccess) return e;
     const size_t n2 = (size_t)2 * a.p.n;
-    for (int ci = 0; ci < nchunk; ci++) {
-        const int t0 = ci * gen, nt = std::min(gen, ntiles - t0);
+    for (int ci = 0; ci < nparts; ci++) {
+        const int t0 = cut[ci], nt = cut[ci + 1] - cut[ci];
         const size_t b0 = (size_t)t0 * c.tile;
         KArgs ac = a;
-        ac.batch = (int)std::min<size_t>((size_t)a.batch - b0, (size_t)nt * c.tile);
+        ac.batch = (int)std::min<size_t>((size_t)(a.batch - hcount) - b0, (size_t)nt * c.tile);
         ac.ws = a.ws + (size_t)t0 * a.tile_bytes;
-        ac.sbus = a.sbus + b0 * n2;
-        ac.v0 = a.v0 + b0 * n2;
-        if (a.v_fb) ac.v_fb = a.v_fb + b0 * n2;
-        ac.ybus = a.ybus + b0 * a.ybus_stride;
-        ac.v_out = a.v_out + b0 * n2;
-        ac.iters_out = a.iters_out + b0;
-        ac.conv_out = a.conv_out + b0;
-        if (a.status_out) ac.status_out = a.status_out + b0;
-        if ((e = launch_phases(c, ac, nt, lds, pp.st[ci % ns])) != hipSuccess) return e;
+        int w;
+        if (order) {
+            // slots now name instances through the order; the boundary arrays stay whole
+            ac.inst = order + hcount + b0;
+            if (hcount > 0) w = 1 + ci % (nw - 1);
+            else w = (nw == 1 || ci == 0) ? 0 : 1 + (ci - 1) % (nw - 1);
+        } else {
+            w = ci % nw;
+            ac.sbus = a.sbus + b0 * n2;
+            ac.v0 = a.v0 + b0 * n2;
+            if (a.v_fb) ac.v_fb = a.v_fb + b0 * n2;
+            ac.ybus = a.ybus + b0 * a.ybus_stride;
+            ac.v_out = a.v_out + b0 * n2;
+            ac.iters_out = a.iters_out + b0;
+            ac.conv_out = a.conv_out + b0;
+            if (a.status_out) ac.status_out = a.status_out + b0;
+        }
+        if ((e = launch_phases(c, ac, nt, lds, wk[w], true, order ? 1 : 0, iters, true, park, ctl_park)) != hipSuccess)
+            return e;
     }
-    for (int i = 0; i < ns; i++) {
-        if ((e = hipEventRecord(pp.fin[i], pp.st[i])) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(user, pp.fin[i], 0)) != hipSuccess) return e;
+    for (int i = 1; i < nw; i++) {
+        if ((e = hipEventRecord(pp.fin[i - 1], wk[i])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(user, pp.fin[i - 1], 0)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -1847,7 +2298,11 @@ static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *
     a.v_fb = v_fb;
     a.ybus_stride = ybus_batched ? (size_t)2 * pl->h.nnzy : 0;
     const bool phases = mode == MODE_SOLVE && c.launch == PF_LAUNCH_PHASES;
-    hipError_t e = phases ? launch_phases_chunked(c, a, ntiles, lds, reinterpret_cast<hipStream_t>(stream), pooled)
+    const TileLayout L = tile_layout(pl->h, c);
+    const bool reorder = phases && c.reorder == PF_REORDER_AUTO &&
+                         workspace_bytes >= L.bytes * (size_t)ntiles + order_bytes(pl->h, c, batch);
+    hipError_t e = phases ? launch_phases_chunked(pl->h, c, a, ntiles, lds, reinterpret_cast<hipStream_t>(stream),
+                                                  pooled, reorder)
                           : launch(c, a, ntiles, lds, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) { set_error(std::string("kernel launch failed: ") + hipGetErrorString(e)); return PF_EDEVICE; }
     return PF_OK;
@@ -2353,7 +2808,7 @@ size_t pf_workspace_bytes(pf_plan plan, int32_t batch, const pf_solve_opts *opts
     std::string err;
     if (!resolve_config(pl->h, opts, c, err, batch)) { set_error(err); return 0; }
     const TileLayout L = tile_layout(pl->h, c);
-    return L.bytes * (size_t)((batch + c.tile - 1) / c.tile);
+    return L.bytes * (size_t)((batch + c.tile - 1) / c.tile) + order_bytes(pl->h, c, batch);
 }
 
 int pf_resolve_opts(pf_plan plan, int32_t batch, const pf_solve_opts *opts, pf_solve_opts *out)
@@ -2370,6 +2825,7 @@ int pf_resolve_opts(pf_plan plan, int32_t batch, const pf_solve_opts *opts, pf_s
     out->schedule = c.schedule;
     out->long_slots = c.n_long;
     out->launch = c.launch;
+    out->reorder = c.reorder;
     return PF_OK;
 }
 
@@ -2396,8 +2852,11 @@ int pf_solve_batch_noalloc(pf_plan plan, int32_t batch, const double *ybus, int3
     if (batch == 0) return PF_OK;
     // the plan must already be resident: uploading it here would allocate
     if (!pl->dev_mem) { set_error("the plan is not resident on a device (pf_analyze found none)"); return PF_EINVAL; }
-    const size_t need = pf_workspace_bytes(plan, batch, opts);
-    if (need == 0) return PF_EINVAL;   // pf_workspace_bytes set the message
+    // the tiles' blocks only: without the stream pool the batch is never reordered
+    Config c;
+    std::string err;
+    if (!resolve_config(pl->h, opts, c, err, batch)) { set_error(err); return PF_EINVAL; }
+    const size_t need = tile_layout(pl->h, c).bytes * (size_t)((batch + c.tile - 1) / c.tile);
     if (need > kScratchBytes) {
         set_error("pf_solve_batch_noalloc: " + std::to_string(batch) + " instances need " + std::to_string(need) +
                   " bytes of scratch, more than its fixed " + std::to_string(kScratchBytes) +

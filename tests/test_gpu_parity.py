@@ -576,3 +576,95 @@ def test_warm_start_per_phase_equals_fused(systems, prec, max_iter):
         assert torch.equal(getattr(rp, f), getattr(rf, f)), f
     if max_iter == 10:
         assert bool(rp.converged[0:24].all()) and bool(rp.converged[48:].all())
+
+
+def assert_same_solves(ra, rk, prec, B):
+    """Two solves of the same batch whose tiles differ: the same statuses and iteration
+    counts except where max |F| lands at the tolerance (at most max(2, B / 1000)
+    instances), and V to rounding where both converged."""
+    st_a, st_k = ra.status.cpu().numpy(), rk.status.cpu().numpy()
+    it_a, it_k = ra.iters.cpu().numpy(), rk.iters.cpu().numpy()
+    differ = (st_a != st_k) | (it_a != it_k)
+    assert differ.sum() <= max(2, B // 1000), np.flatnonzero(differ)[:20]
+    both = (st_a == pf.PF_ST_CONVERGED) & (st_k == pf.PF_ST_CONVERGED) & ~differ
+    dv = np.abs(ra.v.cpu().numpy()[both] - rk.v.cpu().numpy()[both]).max()
+    assert dv <= (1e-9 if prec == pf.PF_FP64 else 1e-7), dv
+
+
+@pytest.mark.parametrize("prec", [pf.PF_FP64, pf.PF_FP32_LU])
+@pytest.mark.parametrize("warm", [False, True])
+def test_reordered_batch_equals_given_order(systems, prec, warm):
+    """A per-phase solve of several generations of tiles reorders the batch hardest first
+    after the first update; the hardest instances finish in a fused launch of smaller tiles.
+    Against the solve in the caller's order and the fused launch, on a 9,000-instance batch
+    of the 1350-bus grid with perturbed angles (longer chains), |V| = 0 starts (non-finite at
+    once) and, with a fallback start, restarts: the same statuses and iteration counts (but
+    for tolerance-boundary cases) and V to rounding."""
+    g, yb, osys, plan = systems["c1_1350bus"]
+    B = 9000
+    assert plan.resolve(B, precision=prec)["launch"] == pf.PF_LAUNCH_PHASES
+    sc = gg.make_scenarios(g, B, 55, "mc")
+    y, s, vflat = to_dev(yb, sc)
+    v0 = vflat.clone()
+    rng = np.random.default_rng(5)
+    hard = torch.from_numpy(rng.choice(B, 600, replace=False)).to(DEV)
+    v0[hard, 1:, 1] += 0.4
+    v0[hard[:40], :, 0] = 0.0
+    kw = {"v_fallback": vflat} if warm else {}
+    ra = pf.solve_batch(plan, y, s, v0, precision=prec, launch=pf.PF_LAUNCH_PHASES, **kw)
+    rk = pf.solve_batch(plan, y, s, v0, precision=prec, launch=pf.PF_LAUNCH_PHASES,
+                        reorder=pf.PF_REORDER_OFF, **kw)
+    rf = pf.solve_batch(plan, y, s, v0, precision=prec, launch=pf.PF_LAUNCH_FUSED, **kw)
+    torch.cuda.synchronize()
+    for f in ("v", "iters", "converged", "status"):
+        assert torch.equal(getattr(rk, f), getattr(rf, f)), f
+    assert_same_solves(ra, rk, prec, B)
+    st = ra.status.cpu().numpy()
+    it = ra.iters.cpu().numpy()
+    assert (st == pf.PF_ST_CONVERGED).sum() > B // 2
+    assert len(np.unique(it)) >= 3                      # the batch mixes short and long chains
+    if not warm:
+        assert (st[hard[:40].cpu().numpy()] != pf.PF_ST_CONVERGED).all()
+
+
+def test_reordered_batch_per_instance_ybus(systems):
+    """The reorder with one set of Ybus values per instance: each slot reads its own
+    instance's values through the order (FP64, 9,000 instances, every third instance on
+    scaled branch admittances)."""
+    g, yb, osys, plan = systems["c1_1350bus"]
+    B = 9000
+    sc = gg.make_scenarios(g, B, 56, "mc")
+    _, s, v = to_dev(yb, sc)
+    scale = np.where(np.arange(B) % 3 == 0, 1.15, 1.0)
+    y = torch.from_numpy(yb.val[None, :] * scale[:, None]).to(DEV)
+    ra = pf.solve_batch(plan, y, s, v, launch=pf.PF_LAUNCH_PHASES)
+    rk = pf.solve_batch(plan, y, s, v, launch=pf.PF_LAUNCH_PHASES, reorder=pf.PF_REORDER_OFF)
+    torch.cuda.synchronize()
+    assert_same_solves(ra, rk, pf.PF_FP64, B)
+    # the scaled instances converge to other voltages than the unscaled ones
+    conv = ra.converged.bool().cpu().numpy()
+    sel = np.flatnonzero(conv & (np.arange(B) % 3 == 0))[:3]
+    ro = osys.solve(sc.sbus[sel], sc.v0[sel])
+    assert not np.allclose(ra.v.cpu().numpy()[sel], ro.v, atol=1e-6)
+
+
+def test_reorder_head_matches_oracle(systems):
+    """Instances that land in the reordered batch's fused head (the largest first steps) and
+    in its per-phase chunks, against the oracle at the FP64 full-solve bar: 9,000 instances
+    of the 1350-bus grid, 300 of them with far-off angles; the oracle checks those 300
+    and 200 others."""
+    g, yb, osys, plan = systems["c1_1350bus"]
+    B = 9000
+    sc = gg.make_scenarios(g, B, 57, "mc")
+    y, s, v = to_dev(yb, sc)
+    rng = np.random.default_rng(9)
+    hard = np.sort(rng.choice(B, 300, replace=False))
+    v0 = sc.v0.copy()
+    v0[hard, 1:, 1] += 0.25
+    r = pf.solve_batch(plan, y, s, torch.from_numpy(v0).to(DEV))
+    torch.cuda.synchronize()
+    sel = np.union1d(hard, rng.choice(np.setdiff1d(np.arange(B), hard), 200, replace=False))
+    ro = osys.solve(sc.sbus[sel], v0[sel])
+    ix = torch.from_numpy(sel).to(DEV)
+    sub = pf.Result(v=r.v[ix], iters=r.iters[ix], converged=r.converged[ix], status=r.status[ix])
+    compare_solve(osys, ro, sub, sc.sbus[sel])
