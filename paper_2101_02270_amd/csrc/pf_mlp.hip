@@ -11,6 +11,7 @@
 // transpose flags on how its operands are read.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -20,6 +21,7 @@
 namespace pf {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h)
@@ -129,6 +131,116 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
             }
 }
 
+// The same product on 128 x 128 tiles of C with gfx950's 16x16x32 BF16 MFMA: 256 threads
+// = 4 wavefronts of 64 x 64 (4 x 4 MFMA tiles each).  K advances in slices of 32: every
+// thread loads 4-byte pairs of both operands' slices (coalesced along each operand's
+// contiguous dimension) for the next slice while the current one is multiplied from LDS,
+// where both operands sit K-contiguous per row / column (an operand stored contiguous
+// along M or N is transposed on the way in).  Needs the contiguous dimension of each
+// stored operand to be even (4-byte pairs) and 4-byte aligned pointers.
+constexpr int TBM = 128, TBN = 128, TBK = 32, TLD = TBK + 8;    // LDS row: 80 B, 16-B aligned
+
+struct TileLoad {
+    uint32_t a[8], b[8];
+};
+
+// the 8 pairs this thread loads of one operand's 128 x 32 slice: operand row r (an M or N
+// index, rows0 + r < rows) and depth k (k0 + k < K); stored contiguous along K (trans =
+// false: element (r, k) at p[r * K + k]) or along r (trans: element (r, k) at p[k * rows + r])
+__device__ __forceinline__ void tile_fetch(uint32_t *dst, const uint16_t *p, int rows0, int rows, int k0, int K,
+                                          bool trans, int tid)
+{
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        const int e = tid + 256 * j;
+        uint32_t v = 0;
+        if (!trans) {
+            const int r = e >> 4, k = k0 + 2 * (e & 15);             // 16 pairs per row
+            if (rows0 + r < rows && k < K) v = *reinterpret_cast<const uint32_t *>(p + (size_t)(rows0 + r) * K + k);
+        } else {
+            const int k = e >> 6, r = rows0 + 2 * (e & 63);          // 64 pairs per depth
+            if (k0 + k < K && r < rows) v = *reinterpret_cast<const uint32_t *>(p + (size_t)(k0 + k) * rows + r);
+        }
+        dst[j] = v;
+    }
+}
+
+__device__ __forceinline__ void tile_store(uint16_t (*sm)[TLD], const uint32_t *src, bool trans, int tid)
+{
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        const int e = tid + 256 * j;
+        if (!trans) {
+            *reinterpret_cast<uint32_t *>(&sm[e >> 4][2 * (e & 15)]) = src[j];
+        } else {
+            const int k = e >> 6, r = 2 * (e & 63);
+            sm[r][k] = (uint16_t)(src[j] & 0xffffu);
+            sm[r + 1][k] = (uint16_t)(src[j] >> 16);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void gemm_bf16_mfma32_kernel(GemmArgs g)
+{
+    __shared__ __align__(16) uint16_t sA[TBM][TLD];   // row m, k contiguous
+    __shared__ __align__(16) uint16_t sB[TBN][TLD];   // column n, k contiguous
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    // A stored [M][K] (k contiguous) unless ta; B stored [N][K] (k contiguous) when tb
+    const bool a_tr = g.ta != 0, b_tr = g.tb == 0;
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    TileLoad ld;
+    tile_fetch(ld.a, g.A, m0, g.M, 0, g.K, a_tr, tid);
+    tile_fetch(ld.b, g.B, n0, g.N, 0, g.K, b_tr, tid);
+    for (int k0 = 0; k0 < g.K; k0 += TBK) {
+        tile_store(sA, ld.a, a_tr, tid);
+        tile_store(sB, ld.b, b_tr, tid);
+        __syncthreads();
+        if (k0 + TBK < g.K) {
+            tile_fetch(ld.a, g.A, m0, g.M, k0 + TBK, g.K, a_tr, tid);
+            tile_fetch(ld.b, g.B, n0, g.N, k0 + TBK, g.K, b_tr, tid);
+        }
+        // operands of a 16x16x32 MFMA: lane holds row / column (lane % 16), k = 8 (lane / 16) + 0..7
+        const int kq = 8 * (lane >> 4);
+        bf16x8 av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) av[i] = *reinterpret_cast<const bf16x8 *>(&sA[wm + 16 * i + (lane & 15)][kq]);
+#pragma unroll
+        for (int j = 0; j < 4; j++) bv[j] = *reinterpret_cast<const bf16x8 *>(&sB[wn + 16 * j + (lane & 15)][kq]);
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // D of a 16x16 MFMA: lane holds column (lane % 16), rows 4 (lane / 16) + 0..3
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int n = n0 + wn + 16 * j + (lane & 15);
+            if (n >= g.N) continue;
+            const float bias = g.bias ? g.bias[n] : 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                if (m >= g.M) continue;
+                const float z = acc[i][j][r] + bias;
+                const size_t o = (size_t)m * g.N + n;
+                if (g.zout) g.zout[o] = z;
+                const float act = g.gelu ? gelu_erf(z) : z;
+                if (g.aout_bf16) g.aout_bf16[o] = f32_to_bf16(act);
+                if (g.aout_f32) g.aout_f32[o] = act;
+            }
+        }
+}
+
 // dZ = dA * GELU'(Z) (or dA) rounded to BF16 for the backward GEMMs, and db = column sums of
 // dZ (FP32, from the unrounded values).  One thread per column, looping over rows.
 __global__ void act_backward_kernel(int M, int N, const float *dA, const float *Z, int gelu, uint16_t *dZ,
@@ -226,14 +338,12 @@ __global__ void warm_v0_kernel(int B, int n, const float *out, const int32_t *fe
         if (!isfinite(va)) va = v_set[o + 1];
         v0[o] = vm;
         v0[o + 1] = va;
-    } else if (f == nf_bus) {
-        // the REF bus is the one bus without a feature slot
-        for (int i = 0; i < n; i++)
-            if (bus_type[i] == PF_BUS_REF) {
-                const size_t o = ((size_t)b * n + i) * 2;
-                v0[o] = v_set[o];
-                v0[o + 1] = v_set[o + 1];
-            }
+    }
+    // the REF bus (the one bus without a feature slot) keeps its set-points
+    if (f < n && bus_type[f] == PF_BUS_REF) {
+        const size_t o = ((size_t)b * n + f) * 2;
+        v0[o] = v_set[o];
+        v0[o + 1] = v_set[o + 1];
     }
 }
 
@@ -262,8 +372,18 @@ int pf_mlp_gemm(int32_t M, int32_t N, int32_t K, int32_t trans_a, int32_t trans_
     if (M < 0 || N < 0 || K < 0 || !a || !b) { set_error("pf_mlp_gemm: bad arguments"); return PF_EINVAL; }
     if (M == 0 || N == 0) return PF_OK;
     GemmArgs g{M, N, K, trans_a ? 1 : 0, trans_b ? 1 : 0, a, b, bias, z_out, act_bf16_out, act_f32_out, gelu ? 1 : 0};
-    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, (hipStream_t)stream, g);
+    // the 128 x 128 MFMA kernel loads 4-byte pairs along each stored operand's contiguous
+    // dimension (K for A, or M when trans_a; N for B, or K when trans_b)
+    const int a_contig = trans_a ? M : K, b_contig = trans_b ? K : N;
+    const bool pairs = a_contig % 2 == 0 && b_contig % 2 == 0 && (reinterpret_cast<uintptr_t>(a) & 3) == 0 &&
+                       (reinterpret_cast<uintptr_t>(b) & 3) == 0;
+    if (pairs) {
+        dim3 grid((N + TBN - 1) / TBN, (M + TBM - 1) / TBM);
+        hipLaunchKernelGGL(gemm_bf16_mfma32_kernel, grid, dim3(256), 0, (hipStream_t)stream, g);
+    } else {
+        dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+        hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, (hipStream_t)stream, g);
+    }
     return launch_status("pf_mlp_gemm");
 }
 
@@ -329,7 +449,8 @@ int pf_mlp_warm_v0(int32_t batch, int32_t n_bus, const float *out, const int32_t
     }
     if (batch == 0) return PF_OK;
     if (batch > 65535) { set_error("pf_mlp_warm_v0: batch above 65535"); return PF_EINVAL; }
-    hipLaunchKernelGGL(warm_v0_kernel, dim3((nf_bus + 1 + 255) / 256, batch), dim3(256), 0, (hipStream_t)stream, batch,
+    hipLaunchKernelGGL(warm_v0_kernel, dim3((std::max(nf_bus, n_bus) + 255) / 256, batch), dim3(256), 0,
+                       (hipStream_t)stream, batch,
                        n_bus, out, feat_bus, nf_bus, mu, sigma, bus_type, v_set, v0);
     return launch_status("pf_mlp_warm_v0");
 }
