@@ -648,11 +648,12 @@ def test_reordered_batch_per_instance_ybus(systems):
     assert not np.allclose(ra.v.cpu().numpy()[sel], ro.v, atol=1e-6)
 
 
-def test_reorder_head_matches_oracle(systems):
-    """Instances that land in the reordered batch's fused head (the largest first steps) and
-    in its per-phase chunks, against the oracle at the FP64 full-solve bar: 9,000 instances
-    of the 1350-bus grid, 300 of them with far-off angles; the oracle checks those 300
-    and 200 others."""
+@pytest.mark.parametrize("prec", [pf.PF_FP64, pf.PF_FP32_LU])
+def test_reorder_head_matches_oracle(systems, prec):
+    """Instances that land in the reordered batch's fused head (the largest first steps, in
+    tiles of four) and in its per-phase chunks, against the oracle at the FP64 full-solve
+    bar or the FP32-LU bar: 9,000 instances of the 1350-bus grid, 300 of them with far-off
+    angles; the oracle checks those 300 and 200 others."""
     g, yb, osys, plan = systems["c1_1350bus"]
     B = 9000
     sc = gg.make_scenarios(g, B, 57, "mc")
@@ -661,10 +662,13 @@ def test_reorder_head_matches_oracle(systems):
     hard = np.sort(rng.choice(B, 300, replace=False))
     v0 = sc.v0.copy()
     v0[hard, 1:, 1] += 0.25
-    r = pf.solve_batch(plan, y, s, torch.from_numpy(v0).to(DEV))
+    r = pf.solve_batch(plan, y, s, torch.from_numpy(v0).to(DEV), precision=prec)
     torch.cuda.synchronize()
     sel = np.union1d(hard, rng.choice(np.setdiff1d(np.arange(B), hard), 200, replace=False))
     ro = osys.solve(sc.sbus[sel], v0[sel])
     ix = torch.from_numpy(sel).to(DEV)
     sub = pf.Result(v=r.v[ix], iters=r.iters[ix], converged=r.converged[ix], status=r.status[ix])
-    compare_solve(osys, ro, sub, sc.sbus[sel])
+    if prec == pf.PF_FP64:
+        compare_solve(osys, ro, sub, sc.sbus[sel])
+    else:
+        compare_fp32lu(osys, ro, sub, sc.sbus[sel], name="c1_1350bus")
