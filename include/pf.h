@@ -362,6 +362,23 @@ int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
             pf_solve_opts *best_out, double *best_ms_out, void *stream);
 
 /*
+ * The tuner's cache across processes.  A key is the plan's pattern hash, the device model
+ * (its architecture name and CU count, not its ordinal), precision, waves, batch, max_iter
+ * and tol, so a cache saved on one device applies to every device of the same kind.
+ *   pf_tune_cache_save   writes every cached entry to the text file at path (replaced):
+ *                        a header line, then one line per entry (key, configuration, ms)
+ *   pf_tune_cache_load   adds the entries of such a file to the cache (an entry with the
+ *                        same key is replaced); PF_EINVAL, cache unchanged, when the file
+ *                        is missing or not such a file
+ *   pf_tune_cache_clear  empties the cache;  pf_tune_cache_size: the number of entries
+ * Host only; no device is needed.
+ */
+int pf_tune_cache_save(const char *path);
+int pf_tune_cache_load(const char *path);
+int pf_tune_cache_clear(void);
+int32_t pf_tune_cache_size(void);
+
+/*
  * pf_branch_flows: branch power flows and losses at voltages v (e.g. a solve's v_out), the
  * quantities a batch of scenarios is run for.  Pi-model branches: series admittance
  * 1/(r + jx), total line charging b_total split half per end.

@@ -29,7 +29,8 @@ EXPORTED = ["pf_analyze", "pf_plan_info", "pf_plan_order", "pf_plan_lu_pattern",
             "pf_eval_step", "pf_plan_destroy", "pf_last_error", "pf_mlp_gemm",
             "pf_mlp_act_backward", "pf_mlp_mse", "pf_mlp_adam", "pf_mlp_to_bf16",
             "pf_mlp_features", "pf_mlp_warm_v0", "pf_queue_create", "pf_queue_add",
-            "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune", "pf_solve_batch_warm",
+            "pf_queue_run", "pf_queue_info", "pf_queue_destroy", "pf_tune", "pf_tune_cache_save",
+            "pf_tune_cache_load", "pf_tune_cache_clear", "pf_tune_cache_size", "pf_solve_batch_warm",
             "pf_resolve_opts", "pf_branch_flows", "pf_plan_schedule", "pf_solve_host",
             "pf_plan_levels", "pf_cpu_solve_batch", "pf_cpu_solve_pivoting", "pf_solve_fallback",
             "pf_solve_batch_noalloc", "pf_plan_ring"]
@@ -127,6 +128,11 @@ def lib():
         L.pf_queue_info.argtypes = [_vp, ctypes.POINTER(_QueueInfo)]
         L.pf_queue_destroy.argtypes = [_vp]
         L.pf_queue_destroy.restype = None
+        L.pf_tune_cache_save.argtypes = [ctypes.c_char_p]
+        L.pf_tune_cache_load.argtypes = [ctypes.c_char_p]
+        L.pf_tune_cache_clear.argtypes = []
+        L.pf_tune_cache_size.argtypes = []
+        L.pf_tune_cache_size.restype = ctypes.c_int32
         L.pf_tune.argtypes = [_vp, i32, _vp, _vp, _vp, ctypes.c_double, i32, i32, i32, i32, i32,
                               ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_double), _vp]
         L.pf_last_error.restype = ctypes.c_char_p
@@ -431,6 +437,24 @@ def tune(plan: Plan, ybus, sbus, v0, tol: float = 1e-8, max_iter: int = 10,
     _check(rc, "pf_tune")
     return ({"precision": best.precision, "tile": best.tile, "waves": best.waves,
              "schedule": best.schedule, "long_slots": best.long_slots}, ms.value)
+
+
+def tune_cache_save(path: str) -> None:
+    """pf_tune_cache_save: write the tuner's cache to a text file."""
+    _check(lib().pf_tune_cache_save(os.fsencode(path)), "pf_tune_cache_save")
+
+
+def tune_cache_load(path: str) -> None:
+    """pf_tune_cache_load: add a saved cache's entries to the tuner's cache."""
+    _check(lib().pf_tune_cache_load(os.fsencode(path)), "pf_tune_cache_load")
+
+
+def tune_cache_clear() -> None:
+    _check(lib().pf_tune_cache_clear(), "pf_tune_cache_clear")
+
+
+def tune_cache_size() -> int:
+    return int(lib().pf_tune_cache_size())
 
 
 class Queue:

@@ -2646,9 +2646,12 @@ static int queue_build(Queue *q)
 }
 
 // ------------------------------------------------------------------ autotuner
+// A tuned configuration belongs to a pattern (its hash), a device model (FNV-1a of the
+// architecture name and the CU count, so that a saved cache applies to any device of the
+// same kind), the precision, the waves asked for, the batch, max_iter and tol.
 struct TuneKey {
-    uint64_t hash;
-    int device, precision, waves, batch, max_iter;
+    uint64_t hash, device;
+    int precision, waves, batch, max_iter;
     double tol;
     bool operator<(const TuneKey &o) const
     {
@@ -2658,6 +2661,18 @@ struct TuneKey {
 };
 static std::mutex g_tune_mu;
 static std::map<TuneKey, std::pair<pf_solve_opts, double>> g_tune_cache;
+
+static int device_model_hash(int dev, uint64_t *out)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) { set_error("hipGetDeviceProperties failed"); return PF_EDEVICE; }
+    uint64_t x = 1469598103934665603ull;
+    for (const char *c = prop.gcnArchName; *c; c++) { x ^= (unsigned char)*c; x *= 1099511628211ull; }
+    const int cus = prop.multiProcessorCount;
+    for (int i = 0; i < 4; i++) { x ^= (unsigned char)(cus >> (8 * i)); x *= 1099511628211ull; }
+    *out = x;
+    return PF_OK;
+}
 
 }  // namespace pf
 
@@ -3025,7 +3040,10 @@ int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
         set_error("the current device differs from the plan's device");
         return PF_EDEVICE;
     }
-    const TuneKey key{pattern_hash(pl->h), dev, precision, waves, batch, max_iter, tol};
+    uint64_t model = 0;
+    const int rcm = device_model_hash(dev, &model);
+    if (rcm != PF_OK) return rcm;
+    const TuneKey key{pattern_hash(pl->h), model, precision, waves, batch, max_iter, tol};
     if (!(flags & PF_TUNE_FORCE)) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto f = g_tune_cache.find(key);
@@ -3147,6 +3165,78 @@ int pf_tune(pf_plan plan, int32_t batch, const double *ybus, const double *sbus,
     *best_out = best_o;
     if (best_ms_out) *best_ms_out = best_ms;
     return PF_OK;
+}
+
+// One line per entry after a header line: the key (pattern hash and device model in hex,
+// precision, waves, batch, max_iter, tol as a C99 hex float), then the configuration
+// (precision, tile, waves, schedule, long_slots, launch, reorder) and the tuned ms per solve.
+static const char *kTuneHeader = "pf_tune_cache 1";
+
+int pf_tune_cache_save(const char *path)
+{
+    if (!path) { set_error("null path"); return PF_EINVAL; }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *f = std::fopen(path, "w");
+    if (!f) { set_error(std::string("cannot open ") + path + " for writing"); return PF_EINVAL; }
+    bool ok = std::fprintf(f, "%s\n", kTuneHeader) > 0;
+    for (const auto &kv : g_tune_cache) {
+        const TuneKey &k = kv.first;
+        const pf_solve_opts &o = kv.second.first;
+        ok = ok && std::fprintf(f, "%016llx %016llx %d %d %d %d %a %d %d %d %d %d %d %d %a\n", (unsigned long long)k.hash,
+                                (unsigned long long)k.device, k.precision, k.waves, k.batch, k.max_iter, k.tol,
+                                o.precision, o.tile, o.waves, o.schedule, o.long_slots, o.launch, o.reorder,
+                                kv.second.second) > 0;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) { set_error(std::string("writing ") + path + " failed"); return PF_EINVAL; }
+    return PF_OK;
+}
+
+int pf_tune_cache_load(const char *path)
+{
+    if (!path) { set_error("null path"); return PF_EINVAL; }
+    FILE *f = std::fopen(path, "r");
+    if (!f) { set_error(std::string("cannot open ") + path); return PF_EINVAL; }
+    char line[512];
+    std::vector<std::pair<TuneKey, std::pair<pf_solve_opts, double>>> got;
+    bool ok = std::fgets(line, sizeof line, f) && std::strncmp(line, kTuneHeader, std::strlen(kTuneHeader)) == 0;
+    int lineno = 1;
+    while (ok && std::fgets(line, sizeof line, f)) {
+        lineno++;
+        if (line[0] == '\n' || line[0] == 0) continue;
+        unsigned long long h = 0, d = 0;
+        TuneKey k{};
+        pf_solve_opts o{};
+        double ms = 0.0;
+        const int n = std::sscanf(line, "%llx %llx %d %d %d %d %la %d %d %d %d %d %d %d %la", &h, &d, &k.precision,
+                                  &k.waves, &k.batch, &k.max_iter, &k.tol, &o.precision, &o.tile, &o.waves,
+                                  &o.schedule, &o.long_slots, &o.launch, &o.reorder, &ms);
+        k.hash = h;
+        k.device = d;
+        ok = n == 15;
+        if (ok) got.push_back({k, {o, ms}});
+    }
+    std::fclose(f);
+    if (!ok) {
+        set_error(std::string(path) + ": not a pf_tune cache (line " + std::to_string(lineno) + ")");
+        return PF_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : got) g_tune_cache[kv.first] = kv.second;
+    return PF_OK;
+}
+
+int pf_tune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
+    return PF_OK;
+}
+
+int32_t pf_tune_cache_size(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return (int32_t)g_tune_cache.size();
 }
 
 int pf_cpu_solve_batch(pf_plan plan, int32_t batch, const double *ybus, const double *sbus, const double *v0,

@@ -169,6 +169,27 @@ def test_tuner_picks_valid_cached_configuration():
     assert (r.v - d.v).abs().max().item() <= 1e-8
 
 
+def test_tune_cache_survives_a_save_and_load(tmp_path):
+    """A tuned entry saved with pf_tune_cache_save and loaded back into an emptied cache is
+    served without timing: same configuration, same ms.  Its key carries the plan's pattern
+    hash."""
+    _, _, plan, y = system("c4_1000bus")
+    s, v = inputs("c4_1000bus", 128, 23)
+    best, ms = pf.tune(plan, y, s, v, precision=pf.PF_FP64, waves=8, reps=1)
+    path = tmp_path / "tune.txt"
+    pf.tune_cache_save(str(path))
+    lines = path.read_text().splitlines()
+    assert lines[0] == "pf_tune_cache 1" and len(lines) == 1 + pf.tune_cache_size()
+    assert any(int(ln.split()[0], 16) == plan.info["pattern_hash"] for ln in lines[1:])
+    pf.tune_cache_clear()
+    assert pf.tune_cache_size() == 0
+    pf.tune_cache_load(str(path))
+    t0 = time.perf_counter()
+    again, ms2 = pf.tune(plan, y, s, v, precision=pf.PF_FP64, waves=8, reps=1)
+    assert again == best and ms2 == ms
+    assert time.perf_counter() - t0 < 0.5
+
+
 def test_queue_group_with_different_long_slot_counts():
     """Items that share precision, tile and waves form one group whose kernel reserves the
     largest LDS of its items; each item lays out its own long working-column slots inside

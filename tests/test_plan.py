@@ -324,3 +324,35 @@ def test_long_panel_ring_never_reuses_rows_in_use(name, order):
             for rp in range(r):
                 if off[rp] < off[r] + rows[r] and off[r] < off[rp] + rows[rp]:
                     assert rp in g_r, (n_long, r, rp)
+
+
+def test_tune_cache_file_round_trip(tmp_path):
+    """pf_tune_cache_save / _load: entries written to a text file come back with every key
+    field and configuration intact (a second save is identical), a file that is not a cache
+    is refused without touching the cache, and a missing file is an error."""
+    pf.tune_cache_clear()
+    assert pf.tune_cache_size() == 0
+    src = tmp_path / "in.txt"
+    src.write_text("pf_tune_cache 1\n"
+                   "00000000000000aa 00000000000000bb 0 8 10000 10 0x1.5798ee2308c3ap-27 0 8 16 0 8 2 0 0x1.7p+4\n"
+                   "00000000000000aa 00000000000000bb 1 0 2000 10 0x1.5798ee2308c3ap-27 1 16 16 1 11 1 1 0x1.1p+5\n")
+    pf.tune_cache_load(str(src))
+    assert pf.tune_cache_size() == 2
+    out1, out2 = tmp_path / "a.txt", tmp_path / "b.txt"
+    pf.tune_cache_save(str(out1))
+    pf.tune_cache_clear()
+    pf.tune_cache_load(str(out1))
+    pf.tune_cache_save(str(out2))
+    assert out1.read_text() == out2.read_text()
+    rows = [ln.split() for ln in out1.read_text().splitlines()[1:]]
+    assert [r[2:6] for r in rows] == [["0", "8", "10000", "10"], ["1", "0", "2000", "10"]]
+    assert float.fromhex(rows[0][6]) == 1e-8 and float.fromhex(rows[1][14]) == 34.0
+    assert rows[1][7:14] == ["1", "16", "16", "1", "11", "1", "1"]
+    bad = tmp_path / "bad.txt"
+    bad.write_text("pf_tune_cache 1\n00aa 00bb 0 8\n")
+    with pytest.raises(pf.PfError, match="not a pf_tune cache"):
+        pf.tune_cache_load(str(bad))
+    assert pf.tune_cache_size() == 2
+    with pytest.raises(pf.PfError):
+        pf.tune_cache_load(str(tmp_path / "missing.txt"))
+    pf.tune_cache_clear()
