@@ -2183,8 +2183,10 @@ static hipError_t launch_phases_chunked(const HostPlan &h, const Config &c, cons
     if ((e = lu_residency(c, lds, &per_cu)) != hipSuccess) return e;
     const int gen = std::max(1, pp.cus * std::max(1, per_cu));
     const int nchunk = (ntiles + gen - 1) / gen;
-    if (nchunk <= 1) return launch_phases(c, a, ntiles, lds, user);
     const int iters = phase_iterations(a);
+    // a batch of at least half a generation is still worth reordering: its few long chains
+    // would otherwise keep every tile's launches going until they end
+    if (nchunk <= 1 && !(reorder && iters > 1 && 2 * ntiles >= gen)) return launch_phases(c, a, ntiles, lds, user);
     const int32_t *order = nullptr;
     double *park = nullptr;
     int4 *ctl_park = nullptr;
