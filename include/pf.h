@@ -89,7 +89,9 @@ typedef struct {
                               the instances by the size of their first step, largest first:
                               the hardest finish in one fused launch of small tiles that
                               keep their CUs (their long iteration chains run at one tile's
-                              latency beside the rest), the others in dense tiles.  Needs
+                              latency beside the rest; with a fallback start the hardest
+                              run their restart beside their first attempt, with the
+                              results of the one-lane rule), the others in dense tiles.  Needs
                               the workspace size pf_workspace_bytes gives, else the
                               caller's order is kept.  PF_REORDER_OFF (1): keep the
                               caller's order.  An instance's results depend on its place

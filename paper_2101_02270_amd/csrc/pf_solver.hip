@@ -85,9 +85,11 @@ struct KArgs {
     // been reordered; null = slot b holds instance b
     const int32_t *inst;
     // a fused launch that resumes a reordered batch: |V| and angle rows and control words
-    // parked after its first update, in instance order
+    // parked after its first update, in instance order; with paired attempts, the first
+    // pair_slots slots hold two per instance (a multiple of the tile size)
     const double *vpark;
     const int4 *cpark;
+    int pair_slots;
 };
 
 __device__ __forceinline__ int inst_of(const KArgs &a, int slot) { return a.inst ? a.inst[slot] : slot; }
@@ -785,8 +787,16 @@ __device__ __forceinline__ void bs_phase(TileCtx<R> &cx, const bool upd_v)
 // The whole Newton loop of one tile (T instances) by one workgroup.  Called by the
 // one-tile-per-workgroup kernel and by the persistent multi-pattern queue kernel.  With
 // RESUME the tile's slots hold instances a.inst[slot] of a reordered batch, which continue
-// from their parked state (see split_park_kernel).
-template <typename R, int T, int NW, bool RESUME = false>
+// from their parked state (see split_park_kernel).  With PAIR (a warm-started batch) the
+// first a.pair_slots slots hold two per instance, a.inst[slot / 2]: the even slot continues
+// the attempt from the given start, the odd slot runs the restart from the fallback point
+// at the same time instead of after it; an attempt that would restart stops there, the odd
+// slot stops once the even one has ended otherwise, and the slot that the one-lane rule
+// would have ended in writes the results (iterations: the updates of both attempts).  The
+// slots after those hold one instance each, a.inst[pair_slots / 2 + slot - pair_slots].
+constexpr int kStRestart = 100;     // internal: an attempt handed over to its restart
+
+template <typename R, int T, int NW, bool RESUME = false, bool PAIR = false>
 __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
 {
     constexpr int SL = 64 / T;          // sub-lanes per instance inside a wavefront
@@ -815,7 +825,10 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
     const int slot = tid / T;
     const int b = tile * T + t;
     const bool valid = b < a.batch;
-    const int bi = RESUME ? (valid ? a.inst[b] : 0) : b;       // the slot's instance
+    const bool paired = PAIR && b < a.pair_slots;
+    const int rank = paired ? b >> 1 : PAIR ? (a.pair_slots >> 1) + b - a.pair_slots : b;
+    const int bi = RESUME ? (valid ? a.inst[rank] : 0) : b;       // the slot's instance
+    const bool flat_lane = paired && (t & 1);   // the flat-start attempt of a paired instance
     const int n = P.n;
     const int N = P.N;
 
@@ -847,7 +860,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                   done, ldone, err, s_prog, s_piv, s_active, s_reset, nprog, nullptr, N};
 
     // ---- boundary layout [B][n][2] -> tile layout [n][T]
-    const double *vsrc = RESUME ? a.vpark : a.v0;
+    const double *vsrc = flat_lane ? a.v_fb : RESUME ? a.vpark : a.v0;
     for (int i = slot; i < n; i += SLOTS) {
         double vm = 1.0, va = 0.0, ps = 0.0, qs = 0.0;
         if (valid) {
@@ -868,16 +881,27 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
             // {status, iterations, updates, active}, {retried, restart pending, updates when
             // the attempt began}, {last max |F| (two words), tile error}
             const int4 c = a.cpark[(size_t)bi * 3], w = a.cpark[(size_t)bi * 3 + 1], x = a.cpark[(size_t)bi * 3 + 2];
-            s_status[t] = c.x; s_iters[t] = c.y; s_nupd[t] = c.z; s_active[t] = c.w;
-            s_retry[t] = w.x; s_reset[t] = w.y; s_base[t] = w.z;
-            s_prevf[t] = __hiloint2double(x.y, x.x);
+            if (!flat_lane) {
+                s_status[t] = c.x; s_iters[t] = c.y; s_nupd[t] = c.z; s_active[t] = c.w;
+                s_retry[t] = w.x; s_reset[t] = w.y; s_base[t] = w.z;
+                s_prevf[t] = __hiloint2double(x.y, x.x);
+            } else {
+                // a plain solve from the fallback point (no restart of its own); needless
+                // when the instance has already stopped or already restarted
+                s_retry[t] = 1;
+                s_active[t] = c.w && !w.x;
+            }
         }
     }
     if (tid == 0) {
         int e0 = 0;
         if (RESUME)
             for (int q = 0; q < T; q++)
-                if (tile * T + q < a.batch) e0 |= a.cpark[(size_t)a.inst[tile * T + q] * 3 + 2].z;
+                if (tile * T + q < a.batch) {
+                    const int bq = tile * T + q;
+                    const int rq = !PAIR ? bq : bq < a.pair_slots ? bq >> 1 : (a.pair_slots >> 1) + bq - a.pair_slots;
+                    e0 |= a.cpark[(size_t)a.inst[rq] * 3 + 2].z;
+                }
         s_err = e0;
     }
     if (tid < NW) s_prog[tid] = 0;
@@ -989,15 +1013,22 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
                 else if (a.v_fb && !s_retry[t] && !(nf < s_prevf[t])) fail = PF_ST_MAXITER;
                 s_prevf[t] = nf;
                 if (fail) {
-                    if (a.v_fb && !s_retry[t]) { s_retry[t] = 1; s_reset[t] = 1; s_base[t] = s_nupd[t]; }
-                    else { s_status[t] = fail; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
+                    if (a.v_fb && !s_retry[t]) {
+                        if (paired) { s_status[t] = kStRestart; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
+                        else { s_retry[t] = 1; s_reset[t] = 1; s_base[t] = s_nupd[t]; }
+                    } else { s_status[t] = fail; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
                 }
             }
         }
         __syncthreads();
         if (tid == 0) {
             int any = 0;
-            for (int q = 0; q < T; q++) any |= s_active[q];
+            for (int q = 0; q < T; q++) {
+                // a flat-start attempt is needless once its warm attempt has ended otherwise
+                if (PAIR && (q & 1) && tile * T + q < a.pair_slots && !s_active[q - 1] && s_status[q - 1] != kStRestart)
+                    s_active[q] = 0;
+                any |= s_active[q];
+            }
             s_any = any;
         }
         __syncthreads();
@@ -1022,8 +1053,10 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         lu_phase<R, T, NW, false>(cx);
         __syncthreads();
         if (tid < T && s_piv[t] && s_active[t] && !s_reset[t] && a.mode == MODE_SOLVE) {
-            if (a.v_fb && !s_retry[t]) { s_retry[t] = 1; s_reset[t] = 1; s_base[t] = s_nupd[t]; }
-            else { s_status[t] = PF_ST_PIVOT; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
+            if (a.v_fb && !s_retry[t]) {
+                if (paired) { s_status[t] = kStRestart; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
+                else { s_retry[t] = 1; s_reset[t] = 1; s_base[t] = s_nupd[t]; }
+            } else { s_status[t] = PF_ST_PIVOT; s_active[t] = 0; s_iters[t] = s_nupd[t]; }
         }
         if (a.mode == MODE_FACTOR) {
             const size_t nnz = (size_t)P.nnzlu;
@@ -1049,8 +1082,9 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         if (tid < T && s_active[t] && !s_reset[t]) s_nupd[t]++;
     }
 
-    // ---- tile layout -> boundary layout
-    if (valid) {
+    // ---- tile layout -> boundary layout (of a pair, the slot whose attempt ended the solve)
+    const bool chosen = !paired || (flat_lane ? s_status[t ^ 1] == kStRestart : s_status[t] != kStRestart);
+    if (valid && chosen) {
         for (int i = slot; i < n; i += SLOTS) {
             const size_t o = ((size_t)bi * n + i) * 2;
             a.v_out[o] = Vm[i * T + t];
@@ -1059,7 +1093,7 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         if (s == 0 && wave == 0) {
             if (a.done_ticks) a.done_ticks[bi] = wall_clock64() - *a.t0;
             const int st = s_err ? PF_ST_INTERNAL : s_status[t];
-            a.iters_out[bi] = s_iters[t];
+            a.iters_out[bi] = s_iters[t] + (flat_lane ? s_iters[t ^ 1] : 0);
             a.conv_out[bi] = st == PF_ST_CONVERGED ? 1 : 0;
             if (a.status_out) a.status_out[bi] = (int8_t)st;
         }
@@ -1076,10 +1110,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
 
 // The head of a reordered batch: its hardest instances finish their Newton iterations in one
 // launch whose workgroups keep their CUs until done, at one tile's latency per iteration.
-template <typename R, int T, int NW>
+template <typename R, int T, int NW, bool PAIR>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void nr_head_kernel(KArgs a)
 {
-    nr_tile_body<R, T, NW, true>(a, blockIdx.x);
+    nr_tile_body<R, T, NW, true, PAIR>(a, blockIdx.x);
 }
 
 // Persistent launch over a queue of work items (one per pattern / batch): workgroups pop
@@ -2146,19 +2180,24 @@ static size_t order_bytes(const HostPlan &h, const Config &c, int64_t batch)
     return bytes;
 }
 
-#define PF_HEAD_LAUNCH(R, TH)                                                                 \
+#define PF_HEAD_LAUNCH(R, TH, PAIR)                                                           \
     {                                                                                         \
-        auto fn = nr_head_kernel<R, TH, 16>;                                                  \
+        auto fn = nr_head_kernel<R, TH, 16, PAIR>;                                            \
         hipError_t e = allow_lds(fn, lds);                                                    \
         if (e != hipSuccess) return e;                                                        \
         hipLaunchKernelGGL(fn, dim3(grid), dim3(16 * 64), lds, st, ah);                       \
         return hipGetLastError();                                                             \
     }
 
-static hipError_t launch_head(const Config &ch, const KArgs &ah, int grid, size_t lds, hipStream_t st)
+// pair: a warm-started batch, two slots per instance (see nr_tile_body)
+static hipError_t launch_head(const Config &ch, const KArgs &ah, int grid, size_t lds, hipStream_t st, bool pair)
 {
-    if (ch.precision == PF_FP64) PF_HEAD_LAUNCH(double, 4)
-    PF_HEAD_LAUNCH(float, 4)
+    if (ch.precision == PF_FP64) {
+        if (pair) PF_HEAD_LAUNCH(double, 4, true)
+        PF_HEAD_LAUNCH(double, 4, false)
+    }
+    if (pair) PF_HEAD_LAUNCH(float, 4, true)
+    PF_HEAD_LAUNCH(float, 4, false)
 }
 
 static hipError_t launch_phases_chunked(const HostPlan &h, const Config &c, const KArgs &a, int ntiles, size_t lds,
@@ -2216,24 +2255,34 @@ static hipError_t launch_phases_chunked(const HostPlan &h, const Config &c, cons
     // streams (on every worker without the reorder).
     // the pool's streams start after the reorder, not after the head
     if ((e = hipEventRecord(pp.start, user)) != hipSuccess) return e;
-    int hcount = 0;
+    int hcount = 0, hgrid = 0;
     if (order && head) {
+        // with a fallback start each head instance takes two slots: its attempt from the
+        // given start and, at the same time, its flat-start restart, so that the longest
+        // chains (an attempt that fails, then a full restart) take the longer of the two
+        // instead of their sum
+        const bool pair = a.v_fb != nullptr;
         const TileLayout Lh = tile_layout(h, ch);
-        hcount = std::min(a.batch, kHeadTiles * ch.tile);
+        // pairs for the first half of the head's tiles, single slots for the rest
+        const int pslots = pair ? std::min(kHeadTiles / 2 * ch.tile, 2 * a.batch) & ~(2 * ch.tile - 1) : 0;
+        hcount = std::min(a.batch, pslots / 2 + kHeadTiles * ch.tile - pslots);
+        const int hslots = hcount + pslots / 2;
         KArgs ah = a;
         ah.ws = head_ws;
         ah.tile_bytes = Lh.bytes; ah.off_y = Lh.off_y; ah.off_vec = Lh.off_vec;
         ah.off_ctl = Lh.off_ctl; ah.off_part = Lh.off_part; ah.nbb = Lh.nbb;
         ah.n_long = ch.n_long;
-        ah.batch = hcount;
+        ah.batch = hslots;
         ah.inst = order;
         ah.vpark = park;
         ah.cpark = ctl_park;
-        if ((e = launch_head(ch, ah, (hcount + ch.tile - 1) / ch.tile, lds_bytes(h, ch), user)) != hipSuccess) return e;
+        ah.pair_slots = pslots;
+        hgrid = (hslots + ch.tile - 1) / ch.tile;
+        if ((e = launch_head(ch, ah, hgrid, lds_bytes(h, ch), user, pair)) != hipSuccess)
+            return e;
     }
     const int btiles = (a.batch - hcount + c.tile - 1) / c.tile;
     // the head's workgroups hold their CUs throughout: a generation of the others fits the rest
-    const int hgrid = (hcount + (head ? ch.tile : 1) - 1) / (head ? ch.tile : 1);
     const int bgen = hcount > 0 ? std::max(1, (pp.cus - std::min(hgrid, pp.cus / 2)) * std::max(1, per_cu)) : gen;
     std::vector<int> cut{0};
     if (order && !head) cut.push_back(std::min(btiles, kHeadTiles));
