@@ -138,82 +138,83 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
 // where both operands sit K-contiguous per row / column (an operand stored contiguous
 // along M or N is transposed on the way in).  Needs the contiguous dimension of each
 // stored operand to be even (4-byte pairs) and 4-byte aligned pointers.
-constexpr int TBM = 128, TBN = 128, TBK = 32, TLD = TBK + 8;    // LDS row: 80 B, 16-B aligned
+constexpr int TBN = 128, TBK = 32, TLD = TBK + 8;    // LDS row: 80 B, 16-B aligned
 
-struct TileLoad {
-    uint32_t a[8], b[8];
-};
-
-// the 8 pairs this thread loads of one operand's 128 x 32 slice: operand row r (an M or N
-// index, rows0 + r < rows) and depth k (k0 + k < K); stored contiguous along K (trans =
+// the NP pairs this thread loads of one operand's ROWS x 32 slice: operand row r (an M or
+// N index, rows0 + r < rows) and depth k (k0 + k < K); stored contiguous along K (trans =
 // false: element (r, k) at p[r * K + k]) or along r (trans: element (r, k) at p[k * rows + r])
+template <int NP, int ROWS>
 __device__ __forceinline__ void tile_fetch(uint32_t *dst, const uint16_t *p, int rows0, int rows, int k0, int K,
                                           bool trans, int tid)
 {
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
+    for (int j = 0; j < NP; j++) {
         const int e = tid + 256 * j;
         uint32_t v = 0;
         if (!trans) {
             const int r = e >> 4, k = k0 + 2 * (e & 15);             // 16 pairs per row
             if (rows0 + r < rows && k < K) v = *reinterpret_cast<const uint32_t *>(p + (size_t)(rows0 + r) * K + k);
         } else {
-            const int k = e >> 6, r = rows0 + 2 * (e & 63);          // 64 pairs per depth
+            const int k = e / (ROWS / 2), r = rows0 + 2 * (e % (ROWS / 2));    // ROWS / 2 pairs per depth
             if (k0 + k < K && r < rows) v = *reinterpret_cast<const uint32_t *>(p + (size_t)(k0 + k) * rows + r);
         }
         dst[j] = v;
     }
 }
 
+template <int NP, int ROWS>
 __device__ __forceinline__ void tile_store(uint16_t (*sm)[TLD], const uint32_t *src, bool trans, int tid)
 {
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
+    for (int j = 0; j < NP; j++) {
         const int e = tid + 256 * j;
         if (!trans) {
             *reinterpret_cast<uint32_t *>(&sm[e >> 4][2 * (e & 15)]) = src[j];
         } else {
-            const int k = e >> 6, r = 2 * (e & 63);
+            const int k = e / (ROWS / 2), r = 2 * (e % (ROWS / 2));
             sm[r][k] = (uint16_t)(src[j] & 0xffffu);
             sm[r + 1][k] = (uint16_t)(src[j] >> 16);
         }
     }
 }
 
+// BM x 128 tiles of C (BM = 128 or 64): 4 wavefronts of BM/2 x 64, (BM/32) x 4 MFMA tiles each
+template <int BM>
 __global__ __launch_bounds__(256) void gemm_bf16_mfma32_kernel(GemmArgs g)
 {
-    __shared__ __align__(16) uint16_t sA[TBM][TLD];   // row m, k contiguous
+    constexpr int MI = BM / 32, NPA = BM * TBK / 2 / 256, NPB = TBN * TBK / 2 / 256;
+    __shared__ __align__(16) uint16_t sA[BM][TLD];    // row m, k contiguous
     __shared__ __align__(16) uint16_t sB[TBN][TLD];   // column n, k contiguous
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * TBN;
+    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * 64;
     // A stored [M][K] (k contiguous) unless ta; B stored [N][K] (k contiguous) when tb
     const bool a_tr = g.ta != 0, b_tr = g.tb == 0;
-    floatx4 acc[4][4];
+    floatx4 acc[MI][4];
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int i = 0; i < MI; i++)
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    TileLoad ld;
-    tile_fetch(ld.a, g.A, m0, g.M, 0, g.K, a_tr, tid);
-    tile_fetch(ld.b, g.B, n0, g.N, 0, g.K, b_tr, tid);
+    uint32_t la[NPA], lb[NPB];
+    tile_fetch<NPA, BM>(la, g.A, m0, g.M, 0, g.K, a_tr, tid);
+    tile_fetch<NPB, TBN>(lb, g.B, n0, g.N, 0, g.K, b_tr, tid);
     for (int k0 = 0; k0 < g.K; k0 += TBK) {
-        tile_store(sA, ld.a, a_tr, tid);
-        tile_store(sB, ld.b, b_tr, tid);
+        tile_store<NPA, BM>(sA, la, a_tr, tid);
+        tile_store<NPB, TBN>(sB, lb, b_tr, tid);
         __syncthreads();
         if (k0 + TBK < g.K) {
-            tile_fetch(ld.a, g.A, m0, g.M, k0 + TBK, g.K, a_tr, tid);
-            tile_fetch(ld.b, g.B, n0, g.N, k0 + TBK, g.K, b_tr, tid);
+            tile_fetch<NPA, BM>(la, g.A, m0, g.M, k0 + TBK, g.K, a_tr, tid);
+            tile_fetch<NPB, TBN>(lb, g.B, n0, g.N, k0 + TBK, g.K, b_tr, tid);
         }
         // operands of a 16x16x32 MFMA: lane holds row / column (lane % 16), k = 8 (lane / 16) + 0..7
         const int kq = 8 * (lane >> 4);
-        bf16x8 av[4], bv[4];
+        bf16x8 av[MI], bv[4];
 #pragma unroll
-        for (int i = 0; i < 4; i++) av[i] = *reinterpret_cast<const bf16x8 *>(&sA[wm + 16 * i + (lane & 15)][kq]);
+        for (int i = 0; i < MI; i++) av[i] = *reinterpret_cast<const bf16x8 *>(&sA[wm + 16 * i + (lane & 15)][kq]);
 #pragma unroll
         for (int j = 0; j < 4; j++) bv[j] = *reinterpret_cast<const bf16x8 *>(&sB[wn + 16 * j + (lane & 15)][kq]);
 #pragma unroll
-        for (int i = 0; i < 4; i++)
+        for (int i = 0; i < MI; i++)
 #pragma unroll
             for (int j = 0; j < 4; j++)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_mfma32_kernel(GemmArgs g)
     }
     // D of a 16x16 MFMA: lane holds column (lane % 16), rows 4 (lane / 16) + 0..3
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int i = 0; i < MI; i++)
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             const int n = n0 + wn + 16 * j + (lane & 15);
@@ -240,6 +241,9 @@ __global__ __launch_bounds__(256) void gemm_bf16_mfma32_kernel(GemmArgs g)
             }
         }
 }
+
+// rows of C per tile: 64 when 128-row tiles would leave CUs without a second workgroup
+constexpr int kGemmSmallTileBelow = 512;
 
 // dZ = dA * GELU'(Z) (or dA) rounded to BF16 for the backward GEMMs, and db = column sums of
 // dZ (FP32, from the unrounded values).  One thread per column, looping over rows.
@@ -378,8 +382,14 @@ int pf_mlp_gemm(int32_t M, int32_t N, int32_t K, int32_t trans_a, int32_t trans_
     const bool pairs = a_contig % 2 == 0 && b_contig % 2 == 0 && (reinterpret_cast<uintptr_t>(a) & 3) == 0 &&
                        (reinterpret_cast<uintptr_t>(b) & 3) == 0;
     if (pairs) {
-        dim3 grid((N + TBN - 1) / TBN, (M + TBM - 1) / TBM);
-        hipLaunchKernelGGL(gemm_bf16_mfma32_kernel, grid, dim3(256), 0, (hipStream_t)stream, g);
+        const int tiles128 = ((N + TBN - 1) / TBN) * ((M + 127) / 128);
+        if (tiles128 < kGemmSmallTileBelow) {
+            dim3 grid((N + TBN - 1) / TBN, (M + 63) / 64);
+            hipLaunchKernelGGL(gemm_bf16_mfma32_kernel<64>, grid, dim3(256), 0, (hipStream_t)stream, g);
+        } else {
+            dim3 grid((N + TBN - 1) / TBN, (M + 127) / 128);
+            hipLaunchKernelGGL(gemm_bf16_mfma32_kernel<128>, grid, dim3(256), 0, (hipStream_t)stream, g);
+        }
     } else {
         dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
         hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, (hipStream_t)stream, g);

@@ -1803,7 +1803,7 @@ static constexpr size_t kLdsLimit = 160 * 1024 - 8192;
 // automatic L is, for each candidate, the most slots (up to kMaxLong) that keep the resident
 // workgroups per CU the batch can use.  batch <= 0 assumes a batch much larger than the GPU.
 static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c, std::string &err,
-                           int64_t batch = 0)
+                           int64_t batch = 0, bool solve = true)
 {
     c.precision = o ? o->precision : PF_FP64;
     c.schedule = o ? o->schedule : 0;
@@ -1880,6 +1880,19 @@ static bool resolve_config(const HostPlan &h, const pf_solve_opts *o, Config &c,
         // launches per iteration would cost more than the phases gain.
         if (c.launch == PF_LAUNCH_AUTO)
             c.launch = h.col_ptr[h.N] >= kPhasesMinLu ? PF_LAUNCH_PHASES : PF_LAUNCH_FUSED;
+        // The model above was fitted to the fused kernel.  The per-phase refactorisation
+        // fits a 16-instance tile of eight wavefronts in one CU's registers; in FP64, when
+        // four long slots still fit and the batch spans two generations of such tiles, one
+        // 16-instance tile per CU out-runs one 8-instance tile of sixteen wavefronts
+        // (1350-bus grid, 10,000 instances: 23.9 -> 23.0 ms per solve; with a single long
+        // slot, the 9000-bus grid's would be 2.4x slower, so that case keeps the model's).
+        if (solve && c.launch == PF_LAUNCH_PHASES && fp64 && !tile && !waves && !long_slots && b >= 2 * 256.0 * 16) {
+            Config k = c;
+            k.tile = 16;
+            k.waves = 8;
+            for (k.n_long = std::min(kMaxLong, h.n_longp); k.n_long >= 4 && lds_bytes(h, k) > kLdsLimit; k.n_long--) {}
+            if (k.n_long >= 4 && lds_bytes(h, k) <= kLdsLimit) c = k;
+        }
         return true;
     }
     err = "the longest LU column (" + std::to_string(h.max_col) + " entries) does not fit in LDS for any "
@@ -2341,7 +2354,8 @@ static int run(pf_plan plan_h, int32_t batch, const double *ybus, const double *
     if (batch == 0) return PF_OK;
     Config c;
     std::string err;
-    if (!resolve_config(pl->h, opts, c, err, batch)) { set_error(err); return PF_EINVAL; }
+    // the single-step entry points run the fused kernel: they take its configuration
+    if (!resolve_config(pl->h, opts, c, err, batch, mode == MODE_SOLVE)) { set_error(err); return PF_EINVAL; }
     KArgs a;
     int ntiles = 0;
     size_t lds = 0;

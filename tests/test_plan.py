@@ -251,7 +251,12 @@ def test_automatic_launch_configuration():
     shapes (many instances of a 1350-bus grid; few of a 9000-bus grid)."""
     g1 = gg.grid("c1_1350bus")
     p1 = pf.Plan.from_ybus(gg.ybus(g1), g1.bus_type)
-    assert (p1.resolve(10000)["tile"], p1.resolve(10000)["waves"]) == (8, 16)
+    # per-phase FP64 on two or more generations of 16-instance tiles with four long slots:
+    # 16 instances x 8 waves (23.0 ms against 23.9 ms for 8 x 16 on 10,000 instances);
+    # fewer instances keep the latency model's 8 x 16
+    assert (p1.resolve(10000)["tile"], p1.resolve(10000)["waves"], p1.resolve(10000)["long_slots"]) == (16, 8, 4)
+    assert (p1.resolve(4000)["tile"], p1.resolve(4000)["waves"]) == (8, 16)
+    assert (p1.resolve(10000, launch=pf.PF_LAUNCH_FUSED)["tile"], p1.resolve(10000, launch=pf.PF_LAUNCH_FUSED)["waves"]) == (8, 16)
     # grids of at least 10,000 LU entries: per-phase launches; small grids: one fused launch
     assert p1.resolve(10000)["launch"] == pf.PF_LAUNCH_PHASES
     assert p1.resolve(10000, launch=pf.PF_LAUNCH_FUSED)["launch"] == pf.PF_LAUNCH_FUSED
@@ -273,7 +278,8 @@ def test_automatic_launch_configuration():
     # slots 20.2 ms.  2,000 scenarios of the 9000-bus grid: FP64 (8, 16) 87.2 / 74.8 ms
     # with 2 / 3 slots (3 is the most that fit), FP32-LU (8, 16) 57.9 / 54.7 / 53.8 / 53.1 ms
     # with 6 / 8 / 10 / 11 (11 is the most that fit).
-    assert p1.resolve(10000)["long_slots"] == 8
+    assert p1.resolve(10000, launch=pf.PF_LAUNCH_FUSED)["long_slots"] == 8
+    assert p1.resolve(4000)["long_slots"] == 8
     assert p1.resolve(10000, precision=pf.PF_FP32_LU)["long_slots"] == 8
     assert p2.resolve(2000)["long_slots"] == 3
     assert p2.resolve(2000, precision=pf.PF_FP32_LU)["long_slots"] == 11
