@@ -48,7 +48,7 @@ void set_error(const std::string &msg) { g_err = msg; }
 enum Mode { MODE_SOLVE = 0, MODE_MISMATCH = 1, MODE_FACTOR = 2, MODE_STEP = 3 };
 
 constexpr int kMBlock = 256;     // threads of a mismatch-kernel workgroup (per-phase launches)
-constexpr size_t kBsZBytes = 48 * 1024;   // per-phase back substitution: LDS for z of the tail
+constexpr size_t kBsZBytes = 48 * 1024;   // per-phase back substitution: most LDS for z of the tail
 constexpr int kPhasesMinLu = 10000;       // automatic launch form: per-phase from this many LU entries
 constexpr int UPD_GROUP = 3;     // column updates whose operand loads are issued together
 constexpr int L_ROWS = 2;        // rows of each source column per lane loaded with its group
@@ -90,6 +90,8 @@ struct KArgs {
     const double *vpark;
     const int4 *cpark;
     int pair_slots;
+    // per-phase back substitution: LDS bytes for z of the highest positions
+    int bs_zbytes;
 };
 
 __device__ __forceinline__ int inst_of(const KArgs &a, int slot) { return a.inst ? a.inst[slot] : slot; }
@@ -1574,7 +1576,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
     int nprog = 0;
     // z of the highest positions (the dense tail, solved first) in LDS after the flags
     R *zlds = reinterpret_cast<R *>(smem_raw + ((P.N + 255) & ~255));
-    const int zb = max(0, P.N - (int)(kBsZBytes / (sizeof(R) * T)));
+    const int zb = max(0, P.N - (int)((size_t)a.bs_zbytes / (sizeof(R) * T)));
     TileCtx<R> cx{a, tid, wave, lane, t, s, valid, reinterpret_cast<R *>(base), reinterpret_cast<R *>(base + a.off_y),
                   vec, vec + nT, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, done, nullptr, &s_err, s_prog,
                   nullptr, s_active, s_reset, nprog, zlds, zb};
@@ -1789,6 +1791,9 @@ static size_t lds_bytes(const HostPlan &h, const Config &c)
 
 static size_t lds_bytes(const HostPlan &h, const Config &c);
 static constexpr size_t kLdsLimit = 160 * 1024 - 8192;
+static constexpr size_t kCuLds = 160 * 1024;    // LDS of a CU
+static constexpr size_t kLdsSlack = 2048;       // allocation rounding of two workgroups
+static constexpr int kWavesPerCu = 16;          // four per SIMD at the kernels' register budget
 
 // Explicit tile/waves are validated.  A zero picks the value that minimises a latency
 // model of the solve: a tile's time grows with the panels each wavefront handles in turn
@@ -1976,16 +1981,37 @@ static hipError_t launch_phases_t(const KArgs &a, int ntiles, size_t lds, hipStr
     auto lu = split_lu_kernel<R, T, NW>;
     auto bs = split_bs_kernel<R, T, NW>;
     hipError_t e = allow_lds(lu, lds);
-    const size_t bs_lds = (((size_t)a.p.N + 255) & ~(size_t)255) + kBsZBytes;
-    if (e == hipSuccess) e = allow_lds(bs, bs_lds);
     if (e != hipSuccess) return e;
+    // The substitution caches z of the dense tail in LDS (kBsZBytes).  When the
+    // refactorization's resident workgroups leave wavefronts free on a CU but little LDS, the
+    // cache shrinks to what is left, so that one chunk's substitution runs beside another
+    // chunk's refactorization instead of waiting for its CU (1350-bus grid, 10,000
+    // instances, FP64 16 x 8 tiles: 22.9 -> 21.7 ms per solve; without free wavefronts, as
+    // in FP32-LU's 16-wave tiles, a smaller cache only slows the substitution).
+    KArgs ab = a;
+    ab.bs_zbytes = (int)kBsZBytes;
+    const size_t flags = ((size_t)a.p.N + 255) & ~(size_t)255;
+    int per_cu = 0;
+    hipFuncAttributes fl{}, fb{};
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lu, NW * 64, lds)) != hipSuccess) return e;
+    if ((e = hipFuncGetAttributes(&fl, reinterpret_cast<const void *>(lu))) != hipSuccess) return e;
+    if ((e = hipFuncGetAttributes(&fb, reinterpret_cast<const void *>(bs))) != hipSuccess) return e;
+    if (per_cu >= 1 && (per_cu + 1) * NW <= kWavesPerCu) {
+        const size_t used = (size_t)per_cu * (lds + fl.sharedSizeBytes) + flags + fb.sharedSizeBytes + kLdsSlack;
+        if (used < kCuLds) {
+            const size_t unit = sizeof(R) * T;
+            ab.bs_zbytes = (int)(std::min(kBsZBytes, kCuLds - used) / unit * unit);
+        }
+    }
+    const size_t bs_lds = flags + (size_t)ab.bs_zbytes;
+    if ((e = allow_lds(bs, bs_lds)) != hipSuccess) return e;
     const int mgrid = std::max(1, std::min(ntiles * a.nbb, 4096));
     if (head) hipLaunchKernelGGL(split_in_kernel<T>, dim3(ntiles), dim3(kMBlock), 0, st, a, vsrc ? vsrc : a.v0, csrc);
     for (int k = it0; k < it1; k++) {
         hipLaunchKernelGGL(split_v_kernel<T>, dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles);
         hipLaunchKernelGGL((split_m_kernel<R, T>), dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles, 1);
         hipLaunchKernelGGL(lu, dim3(ntiles), dim3(NW * 64), lds, st, a);
-        hipLaunchKernelGGL(bs, dim3(ntiles), dim3(NW * 64), bs_lds, st, a);
+        hipLaunchKernelGGL(bs, dim3(ntiles), dim3(NW * 64), bs_lds, st, ab);
     }
     if (tail) {
         hipLaunchKernelGGL(split_v_kernel<T>, dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles);
