@@ -48,6 +48,10 @@ void set_error(const std::string &msg) { g_err = msg; }
 enum Mode { MODE_SOLVE = 0, MODE_MISMATCH = 1, MODE_FACTOR = 2, MODE_STEP = 3 };
 
 constexpr int kMBlock = 256;     // threads of a mismatch-kernel workgroup (per-phase launches)
+// admittance entries whose operands the per-phase mismatch kernel loads together
+// (1350-bus grid, 10,000 instances: 27.1 -> 26.5 ms per FP64 solve in the given order;
+// eight entries are slower than four)
+constexpr int kMRow = 4;
 constexpr size_t kBsZBytes = 48 * 1024;   // per-phase back substitution: most LDS for z of the tail
 constexpr int kPhasesMinLu = 10000;       // automatic launch form: per-phase from this many LU entries
 constexpr int UPD_GROUP = 3;     // column updates whose operand loads are issued together
@@ -786,6 +790,64 @@ __device__ __forceinline__ void bs_phase(TileCtx<R> &cx, const bool upd_v)
     }
 }
 
+// One bus's row of I = Y V (Eq. 1) for instance lane t: ir + j ii = sum_k Y_ik V_k in entry
+// order, the diagonal entry's admittance and index, and, with build, the off-diagonal
+// Jacobian entries of the bus's equations written into the LU array (Sec. 3.1.2): with
+// w = V_i conj(Y_ik V_k), dS_i/dangle_k = -j w and dS_i/d|V_k| = w / |V_k|.  The row goes in
+// groups of G entries whose operands are all loaded before any of the group's stores (a
+// store could alias a later load, so entry by entry the loads would wait for them); the
+// fused kernel, at its register limit, takes G = 1.
+template <typename R, int T, int G>
+__device__ __forceinline__ void bus_row(const DevPlan &P, const double2 *yrow, const double2 *Vc, const double *Vm,
+                                        R *LU, int i, int t, double2 vv, bool build, double &ir, double &ii,
+                                        double2 &ydg, int &qdg)
+{
+    ir = 0.0;
+    ii = 0.0;
+    ydg = make_double2(0.0, 0.0);
+    qdg = -1;
+    const int q1 = P.yrp[i + 1];
+    for (int qb = P.yrp[i]; qb < q1; qb += G) {
+        int kx[G];
+        double2 yx[G], vx[G];
+        double vmk[G];
+        JPos jx[G];
+#pragma unroll
+        for (int x = 0; x < G; x++) {
+            const int q = min(qb + x, q1 - 1);
+            kx[x] = P.yci[q];
+            yx[x] = yrow[q];
+            if (build) jx[x] = P.jpos[q];
+        }
+#pragma unroll
+        for (int x = 0; x < G; x++) {
+            vx[x] = Vc[kx[x] * T + t];
+            if (build) vmk[x] = Vm[kx[x] * T + t];
+        }
+#pragma unroll
+        for (int x = 0; x < G; x++) {
+            if (qb + x >= q1) break;
+            const int k = kx[x];
+            const double2 y = yx[x], v = vx[x];
+            const double cr = y.x * v.x - y.y * v.y, ci = y.x * v.y + y.y * v.x;     // Y_ik V_k
+            ir += cr;
+            ii += ci;
+            if (k == i) {
+                ydg = y;
+                qdg = qb + x;
+            } else if (build) {
+                const JPos jp = jx[x];
+                const double inv = 1.0 / vmk[x];
+                const double wr = vv.x * cr + vv.y * ci, wi = vv.y * cr - vv.x * ci;
+                if (jp.pt >= 0) LU[(size_t)jp.pt * T + t] = (R)wi;
+                if (jp.pv >= 0) LU[(size_t)jp.pv * T + t] = (R)(wr * inv);
+                if (jp.qt >= 0) LU[(size_t)jp.qt * T + t] = (R)(-wr);
+                if (jp.qv >= 0) LU[(size_t)jp.qv * T + t] = (R)(wi * inv);
+            }
+        }
+    }
+}
+
 // The whole Newton loop of one tile (T instances) by one workgroup.  Called by the
 // one-tile-per-workgroup kernel and by the persistent multi-pattern queue kernel.  With
 // RESUME the tile's slots hold instances a.inst[slot] of a reordered batch, which continue
@@ -941,29 +1003,10 @@ __device__ __forceinline__ void nr_tile_body(const KArgs &a, const int tile)
         int bad = 0;
         for (int i = slot; i < n; i += SLOTS) {
             const double2 vv = Vc[i * T + t];
-            double ir = 0.0, ii = 0.0;
-            double2 ydg = make_double2(0.0, 0.0);
-            int qdg = -1;
-            for (int q = P.yrp[i]; q < P.yrp[i + 1]; q++) {
-                const int k = P.yci[q];
-                const double2 y = yrow[q];
-                const double2 v = Vc[k * T + t];
-                const double cr = y.x * v.x - y.y * v.y, ci = y.x * v.y + y.y * v.x;     // Y_ik V_k
-                ir += cr;
-                ii += ci;
-                if (k == i) {
-                    ydg = y;
-                    qdg = q;
-                } else if (build) {
-                    const JPos jp = P.jpos[q];
-                    const double inv = 1.0 / Vm[k * T + t];
-                    const double wr = vv.x * cr + vv.y * ci, wi = vv.y * cr - vv.x * ci;
-                    if (jp.pt >= 0) LU[(size_t)jp.pt * T + t] = (R)wi;
-                    if (jp.pv >= 0) LU[(size_t)jp.pv * T + t] = (R)(wr * inv);
-                    if (jp.qt >= 0) LU[(size_t)jp.qt * T + t] = (R)(-wr);
-                    if (jp.qv >= 0) LU[(size_t)jp.qv * T + t] = (R)(wi * inv);
-                }
-            }
+            double ir, ii;
+            double2 ydg;
+            int qdg;
+            bus_row<R, T, 1>(P, yrow, Vc, Vm, LU, i, t, vv, build, ir, ii, ydg, qdg);
             const double sr = vv.x * ir + vv.y * ii, si = vv.y * ir - vv.x * ii;       // S_i
             if (build && qdg >= 0) {
                 const JPos jp = P.jpos[qdg];
@@ -1380,29 +1423,10 @@ __global__ __launch_bounds__(kMBlock) void split_m_kernel(KArgs a, int ntiles, i
         int bad = 0;
         if (i < n) {
             const double2 vv = Vc[i * T + t];
-            double ir = 0.0, ii = 0.0;
-            double2 ydg = make_double2(0.0, 0.0);
-            int qdg = -1;
-            for (int q = P.yrp[i]; q < P.yrp[i + 1]; q++) {
-                const int k = P.yci[q];
-                const double2 y = yrow[q];
-                const double2 v = Vc[k * T + t];
-                const double cr = y.x * v.x - y.y * v.y, ci = y.x * v.y + y.y * v.x;     // Y_ik V_k
-                ir += cr;
-                ii += ci;
-                if (k == i) {
-                    ydg = y;
-                    qdg = q;
-                } else if (build) {
-                    const JPos jp = P.jpos[q];
-                    const double inv = 1.0 / Vm[k * T + t];
-                    const double wr = vv.x * cr + vv.y * ci, wi = vv.y * cr - vv.x * ci;
-                    if (jp.pt >= 0) LU[(size_t)jp.pt * T + t] = (R)wi;
-                    if (jp.pv >= 0) LU[(size_t)jp.pv * T + t] = (R)(wr * inv);
-                    if (jp.qt >= 0) LU[(size_t)jp.qt * T + t] = (R)(-wr);
-                    if (jp.qv >= 0) LU[(size_t)jp.qv * T + t] = (R)(wi * inv);
-                }
-            }
+            double ir, ii;
+            double2 ydg;
+            int qdg;
+            bus_row<R, T, kMRow>(P, yrow, Vc, Vm, LU, i, t, vv, build, ir, ii, ydg, qdg);
             const double sr = vv.x * ir + vv.y * ii, si = vv.y * ir - vv.x * ii;       // S_i
             if (build && qdg >= 0) {
                 const JPos jp = P.jpos[qdg];
