@@ -52,7 +52,7 @@ constexpr int kMBlock = 256;     // threads of a mismatch-kernel workgroup (per-
 // (1350-bus grid, 10,000 instances: 27.1 -> 26.5 ms per FP64 solve in the given order;
 // eight entries are slower than four)
 constexpr int kMRow = 4;
-constexpr size_t kBsZBytes = 48 * 1024;   // per-phase back substitution: most LDS for z of the tail
+constexpr size_t kBsZBytes = 48 * 1024;   // wide per-phase back substitution: LDS for z of the tail
 constexpr int kPhasesMinLu = 10000;       // automatic launch form: per-phase from this many LU entries
 constexpr int UPD_GROUP = 3;     // column updates whose operand loads are issued together
 constexpr int L_ROWS = 2;        // rows of each source column per lane loaded with its group
@@ -1232,12 +1232,30 @@ __device__ __forceinline__ double *tile_prevf(const KArgs &a, int tile)
 
 // Boundary rows [B][n][2] <-> tile layout [n][T], through LDS: each round moves kMBlock / T
 // buses of the tile's T instances, reading (or writing) every instance's row segment
-// contiguously and the tile layout contiguously.  Slot b's row is its instance's.
+// contiguously and the tile layout contiguously.  Slot b's row is its instance's.  The
+// grid's y dimension splits a tile's buses into ranges of kStageRounds rounds, one
+// workgroup each (one workgroup per tile left most CUs idle and ran its rounds one after
+// another: 9000-bus grid, 2,000 instances, 0.53 ms for the layout in).
+constexpr int kStageRounds = 8;
 template <int T>
 struct RowStage {
     static constexpr int CH = kMBlock / T;
     double v[2][2 * CH][T + 1];
 };
+template <int T>
+static int stage_splits(int n)
+{
+    constexpr int per = kStageRounds * RowStage<T>::CH;
+    return (n + per - 1) / per;
+}
+// the buses [*i_lo, *i_hi) of workgroup blockIdx.y
+template <int T>
+__device__ __forceinline__ void stage_range(int n, int *i_lo, int *i_hi)
+{
+    constexpr int per = kStageRounds * RowStage<T>::CH;
+    *i_lo = blockIdx.y * per;
+    *i_hi = min(n, *i_lo + per);
+}
 
 // layout in: |V| and angle from vsrc (the start v0, or the rows parked after the first
 // update), the P and Q set points from sbus; instance states either initialised or, with
@@ -1257,8 +1275,10 @@ __global__ __launch_bounds__(kMBlock) void split_in_kernel(KArgs a, const double
     __syncthreads();
     double *vec = reinterpret_cast<double *>(a.ws + (size_t)tile * a.tile_bytes + a.off_vec);
     const size_t nT = (size_t)n * T;
-    for (int i0 = 0; i0 < n; i0 += CH) {
-        const int nb = min(CH, n - i0);
+    int i_lo, i_hi;
+    stage_range<T>(n, &i_lo, &i_hi);
+    for (int i0 = i_lo; i0 < i_hi; i0 += CH) {
+        const int nb = min(CH, i_hi - i0);
         for (int e = tid; e < T * 2 * CH; e += kMBlock) {
             const int t = e / (2 * CH), w = e - t * (2 * CH);      // w = 2 * bus + (0 |V| or P, 1 angle or Q)
             const int row = s_row[t];
@@ -1282,6 +1302,7 @@ __global__ __launch_bounds__(kMBlock) void split_in_kernel(KArgs a, const double
         }
         __syncthreads();
     }
+    if (blockIdx.y != 0) return;
     int4 *ctl = tile_ctl<T>(a, tile);
     __shared__ int s_act[T], s_err[T];
     if (tid < T) {
@@ -1332,8 +1353,10 @@ __global__ __launch_bounds__(kMBlock) void split_park_kernel(KArgs a, double *pa
     __syncthreads();
     const double *vec = reinterpret_cast<const double *>(a.ws + (size_t)tile * a.tile_bytes + a.off_vec);
     const size_t nT = (size_t)n * T;
-    for (int i0 = 0; i0 < n; i0 += CH) {
-        const int nb = min(CH, n - i0);
+    int i_lo, i_hi;
+    stage_range<T>(n, &i_lo, &i_hi);
+    for (int i0 = i_lo; i0 < i_hi; i0 += CH) {
+        const int nb = min(CH, i_hi - i0);
         for (int e = tid; e < nb * T; e += kMBlock) {
             const int il = e / T, t = e - il * T;
             const size_t o = (size_t)(i0 + il) * T + t;
@@ -1348,7 +1371,7 @@ __global__ __launch_bounds__(kMBlock) void split_park_kernel(KArgs a, double *pa
         }
         __syncthreads();
     }
-    if (tid < T && s_row[tid] >= 0) {
+    if (blockIdx.y == 0 && tid < T && s_row[tid] >= 0) {
         const int4 *ctl = tile_ctl<T>(a, tile);
         const size_t r = (size_t)s_row[tid] * 3;
         ctl_park[r] = ctl[tid];
@@ -1619,7 +1642,8 @@ __global__ __launch_bounds__(kMBlock) void split_out_kernel(KArgs a)
     const bool valid = b < a.batch;
     int4 *ctl = tile_ctl<T>(a, tile);
     const int *tf = reinterpret_cast<const int *>(ctl + T);
-    if (tid < T && tf[0]) {
+    const bool first = blockIdx.y == 0;     // the workgroup that decides and writes the states
+    if (first && tid < T && tf[0]) {
         int rs = 0;
         if (split_decide<T>(a, tile, t, &rs) && rs) {
             // a restart requested at the last decision has no iteration left
@@ -1636,8 +1660,10 @@ __global__ __launch_bounds__(kMBlock) void split_out_kernel(KArgs a)
     const int n = a.p.n;
     const double *vec = reinterpret_cast<const double *>(a.ws + (size_t)tile * a.tile_bytes + a.off_vec);
     const size_t nT = (size_t)n * T;
-    for (int i0 = 0; i0 < n; i0 += CH) {
-        const int nb = min(CH, n - i0);
+    int i_lo, i_hi;
+    stage_range<T>(n, &i_lo, &i_hi);
+    for (int i0 = i_lo; i0 < i_hi; i0 += CH) {
+        const int nb = min(CH, i_hi - i0);
         for (int e = tid; e < nb * T; e += kMBlock) {
             const int il = e / T, tt = e - il * T;
             const size_t o = (size_t)(i0 + il) * T + tt;
@@ -1652,7 +1678,7 @@ __global__ __launch_bounds__(kMBlock) void split_out_kernel(KArgs a)
         }
         __syncthreads();
     }
-    if (tid < T && valid) {
+    if (first && tid < T && valid) {
         const int bi = s_row[t];
         const int4 c = ctl[t];
         const int st_ = tf[1] ? PF_ST_INTERNAL : c.x;
@@ -1815,9 +1841,6 @@ static size_t lds_bytes(const HostPlan &h, const Config &c)
 
 static size_t lds_bytes(const HostPlan &h, const Config &c);
 static constexpr size_t kLdsLimit = 160 * 1024 - 8192;
-static constexpr size_t kCuLds = 160 * 1024;    // LDS of a CU
-static constexpr size_t kLdsSlack = 2048;       // allocation rounding of two workgroups
-static constexpr int kWavesPerCu = 16;          // four per SIMD at the kernels' register budget
 
 // Explicit tile/waves are validated.  A zero picks the value that minimises a latency
 // model of the solve: a tile's time grows with the panels each wavefront handles in turn
@@ -2006,31 +2029,19 @@ static hipError_t launch_phases_t(const KArgs &a, int ntiles, size_t lds, hipStr
     auto bs = split_bs_kernel<R, T, NW>;
     hipError_t e = allow_lds(lu, lds);
     if (e != hipSuccess) return e;
-    // The substitution caches z of the dense tail in LDS (kBsZBytes).  When the
-    // refactorization's resident workgroups leave wavefronts free on a CU but little LDS, the
-    // cache shrinks to what is left, so that one chunk's substitution runs beside another
-    // chunk's refactorization instead of waiting for its CU (1350-bus grid, 10,000
-    // instances, FP64 16 x 8 tiles: 22.9 -> 21.7 ms per solve; without free wavefronts, as
-    // in FP32-LU's 16-wave tiles, a smaller cache only slows the substitution).
+    // The substitution's dynamic LDS: its rows' publication bytes and, in the wide form only,
+    // z of the dense tail (kBsZBytes).  Without that cache a substitution workgroup fits
+    // beside a refactorization workgroup on a CU whenever the wavefronts allow, so one
+    // chunk's substitution runs beside another chunk's refactorization instead of waiting
+    // for its CU (1350-bus grid, 10,000 instances, FP64 16 x 8 tiles: 22.9 -> 21.7 ms per
+    // solve with the 48 KB that used to be reserved whatever the form).
     KArgs ab = a;
-    ab.bs_zbytes = (int)kBsZBytes;
-    const size_t flags = ((size_t)a.p.N + 255) & ~(size_t)255;
-    int per_cu = 0;
-    hipFuncAttributes fl{}, fb{};
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lu, NW * 64, lds)) != hipSuccess) return e;
-    if ((e = hipFuncGetAttributes(&fl, reinterpret_cast<const void *>(lu))) != hipSuccess) return e;
-    if ((e = hipFuncGetAttributes(&fb, reinterpret_cast<const void *>(bs))) != hipSuccess) return e;
-    if (per_cu >= 1 && (per_cu + 1) * NW <= kWavesPerCu) {
-        const size_t used = (size_t)per_cu * (lds + fl.sharedSizeBytes) + flags + fb.sharedSizeBytes + kLdsSlack;
-        if (used < kCuLds) {
-            const size_t unit = sizeof(R) * T;
-            ab.bs_zbytes = (int)(std::min(kBsZBytes, kCuLds - used) / unit * unit);
-        }
-    }
-    const size_t bs_lds = flags + (size_t)ab.bs_zbytes;
+    ab.bs_zbytes = kWideBs<R> ? (int)kBsZBytes : 0;
+    const size_t bs_lds = (((size_t)a.p.N + 255) & ~(size_t)255) + (size_t)ab.bs_zbytes;
     if ((e = allow_lds(bs, bs_lds)) != hipSuccess) return e;
     const int mgrid = std::max(1, std::min(ntiles * a.nbb, 4096));
-    if (head) hipLaunchKernelGGL(split_in_kernel<T>, dim3(ntiles), dim3(kMBlock), 0, st, a, vsrc ? vsrc : a.v0, csrc);
+    const dim3 sgrid(ntiles, stage_splits<T>(a.p.n));
+    if (head) hipLaunchKernelGGL(split_in_kernel<T>, sgrid, dim3(kMBlock), 0, st, a, vsrc ? vsrc : a.v0, csrc);
     for (int k = it0; k < it1; k++) {
         hipLaunchKernelGGL(split_v_kernel<T>, dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles);
         hipLaunchKernelGGL((split_m_kernel<R, T>), dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles, 1);
@@ -2040,7 +2051,7 @@ static hipError_t launch_phases_t(const KArgs &a, int ntiles, size_t lds, hipStr
     if (tail) {
         hipLaunchKernelGGL(split_v_kernel<T>, dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles);
         hipLaunchKernelGGL((split_m_kernel<R, T>), dim3(mgrid), dim3(kMBlock), 0, st, a, ntiles, 0);
-        hipLaunchKernelGGL(split_out_kernel<T>, dim3(ntiles), dim3(kMBlock), 0, st, a);
+        hipLaunchKernelGGL(split_out_kernel<T>, sgrid, dim3(kMBlock), 0, st, a);
     }
     return hipGetLastError();
 }
@@ -2063,7 +2074,8 @@ static hipError_t launch_reorder_t(const KArgs &a, int ntiles, hipStream_t st, u
         hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(1024), 0, st, hist, 256 * nblk);
         hipLaunchKernelGGL(sort_scatter_kernel, dim3(nblk), dim3(256), 0, st, ki, ii, ko, io, n, 8 * pass, hist);
     }
-    hipLaunchKernelGGL(split_park_kernel<T>, dim3(ntiles), dim3(kMBlock), 0, st, a, park, ctl_park);
+    hipLaunchKernelGGL(split_park_kernel<T>, dim3(ntiles, stage_splits<T>(a.p.n)), dim3(kMBlock), 0, st, a, park,
+                       ctl_park);
     return hipGetLastError();
 }
 
