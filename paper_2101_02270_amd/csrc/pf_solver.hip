@@ -2305,7 +2305,12 @@ static hipError_t launch_phases_chunked(const HostPlan &h, const Config &c, cons
     double *park = nullptr;
     int4 *ctl_park = nullptr;
     Config ch;
-    const bool head = reorder && head_config(h, c, ch);
+    // The hardest instances run as the fused head (below), except in an FP32-LU flat-start
+    // batch of at most one generation: there the per-phase kernels, which hold their FP32
+    // working set in registers without spilling, take them as the first chunk (9000-bus
+    // grid, 2,000 instances: 43.3 -> 41.5 ms per solve; in FP64 the fused head is the faster,
+    // 53.1 against 58.5 ms, and with more generations the bulk sets the time)
+    const bool head = reorder && head_config(h, c, ch) && !(c.precision == PF_FP32_LU && nchunk <= 1 && !a.v_fb);
     char *head_ws = nullptr;
     if (reorder && iters > 1) {
         char *ob = a.ws + (size_t)ntiles * a.tile_bytes;
