@@ -49,9 +49,10 @@ enum Mode { MODE_SOLVE = 0, MODE_MISMATCH = 1, MODE_FACTOR = 2, MODE_STEP = 3 };
 
 constexpr int kMBlock = 256;     // threads of a mismatch-kernel workgroup (per-phase launches)
 // admittance entries whose operands the per-phase mismatch kernel loads together
-// (1350-bus grid, 10,000 instances: 27.1 -> 26.5 ms per FP64 solve in the given order;
-// eight entries are slower than four)
-constexpr int kMRow = 4;
+// (1350-bus grid, 10,000 instances, FP64 solves in the given order: 27.1 ms one at a time,
+// 25.4 with two, 25.5 with three, 26.5 with four, 27.5 with eight: more entries hold more
+// registers, and fewer wavefronts fit)
+constexpr int kMRow = 2;
 constexpr size_t kBsZBytes = 48 * 1024;   // wide per-phase back substitution: LDS for z of the tail
 constexpr int kPhasesMinLu = 10000;       // automatic launch form: per-phase from this many LU entries
 constexpr int UPD_GROUP = 3;     // column updates whose operand loads are issued together
