@@ -2227,10 +2227,11 @@ struct PhasePool {
 static std::mutex g_pool_mu;
 static PhasePool g_pool[64];
 
-// The head of a reordered batch runs the fused kernel in a low-latency form: tiles of four
-// instances (sixteen sub-lanes each), sixteen wavefronts, and as many long slots as fit
-// (measured per iteration of one tile on the 1350-bus grid: FP64 0.56 ms against 0.62 ms
-// with eight instances; four instances also beat two over whole solves).
+// The head of a reordered batch runs in a low-latency form: tiles of four instances (sixteen
+// sub-lanes each), sixteen wavefronts, and as many long slots as fit (measured per iteration
+// of one tile on the 1350-bus grid: FP64 0.56 ms against 0.62 ms with eight instances; four
+// instances also beat two over whole solves), in the fused kernel or, for FP64 from the
+// given start, as per-phase launches.
 static bool head_config(const HostPlan &h, const Config &c, Config &ch)
 {
     ch = c;
@@ -2306,11 +2307,11 @@ static hipError_t launch_phases_chunked(const HostPlan &h, const Config &c, cons
     double *park = nullptr;
     int4 *ctl_park = nullptr;
     Config ch;
-    // The hardest instances run as the fused head (below), except in an FP32-LU flat-start
-    // batch of at most one generation: there the per-phase kernels, which hold their FP32
-    // working set in registers without spilling, take them as the first chunk (9000-bus
-    // grid, 2,000 instances: 43.3 -> 41.5 ms per solve; in FP64 the fused head is the faster,
-    // 53.1 against 58.5 ms, and with more generations the bulk sets the time)
+    // The hardest instances run as the head (below), except in an FP32-LU flat-start batch
+    // of at most one generation: there they are the first chunk of the batch's own tiles
+    // (9000-bus grid, 2,000 instances: 43.3 -> 41.5 ms per solve against the fused FP32 head,
+    // which spills; in FP64 the head's four-instance tiles are the faster, 53.1 against
+    // 58.5 ms with the batch's eight, and with more generations the bulk sets the time)
     const bool head = reorder && head_config(h, c, ch) && !(c.precision == PF_FP32_LU && nchunk <= 1 && !a.v_fb);
     char *head_ws = nullptr;
     if (reorder && iters > 1) {
@@ -2330,8 +2331,9 @@ static hipError_t launch_phases_chunked(const HostPlan &h, const Config &c, cons
         order = i0;
     }
     // With the reorder, the head (the hardest instances: kHeadTiles tiles of the head
-    // configuration) runs as one fused launch on the caller's stream: its workgroups hold
-    // their CUs until their long iteration chains end, at one tile's latency per iteration.
+    // configuration) runs alone on the caller's stream (one fused launch, or its per-phase
+    // launches): its workgroups run their long iteration chains at one tile's latency per
+    // iteration.
     // The other instances follow in one-generation chunks of per-phase launches on the pool's
     // streams (on every worker without the reorder).
     // the pool's streams start after the reorder, not after the head
@@ -2359,7 +2361,17 @@ static hipError_t launch_phases_chunked(const HostPlan &h, const Config &c, cons
         ah.cpark = ctl_park;
         ah.pair_slots = pslots;
         hgrid = (hslots + ch.tile - 1) / ch.tile;
-        if ((e = launch_head(ch, ah, hgrid, lds_bytes(h, ch), user, pair)) != hipSuccess)
+        if (!pair && ch.precision == PF_FP64) {
+            // FP64 from the given start: the head's tiles as per-phase launches, whose
+            // refactorization keeps its wider loads without spilling (9000-bus grid, 2,000
+            // instances: 53.1 -> 51.8 ms per solve; the 1350-bus grid unchanged); a
+            // warm-started head needs the fused kernel's paired slots
+            Config cp = ch;
+            cp.launch = PF_LAUNCH_PHASES;
+            if ((e = launch_phases(cp, ah, hgrid, lds_bytes(h, cp), user, true, 1, iters, true, park, ctl_park)) !=
+                hipSuccess)
+                return e;
+        } else if ((e = launch_head(ch, ah, hgrid, lds_bytes(h, ch), user, pair)) != hipSuccess)
             return e;
     }
     const int btiles = (a.batch - hcount + c.tile - 1) / c.tile;
