@@ -653,8 +653,9 @@ def test_reordered_batch_per_instance_ybus(systems):
 
 @pytest.mark.parametrize("prec", [pf.PF_FP64, pf.PF_FP32_LU])
 def test_reorder_head_matches_oracle(systems, prec):
-    """Instances that land in the reordered batch's fused head (the largest first steps, in
-    tiles of four) and in its per-phase chunks, against the oracle at the FP64 full-solve
+    """Instances that land in the reordered batch's head (the largest first steps, in tiles
+    of four: per-phase launches in FP64, the fused kernel in FP32-LU) and in its per-phase
+    chunks, against the oracle at the FP64 full-solve
     bar or the FP32-LU bar: 9,000 instances of the 1350-bus grid, 300 of them with far-off
     angles; the oracle checks those 300 and 200 others."""
     g, yb, osys, plan = systems["c1_1350bus"]
