@@ -2218,6 +2218,10 @@ static int make_args(Plan *pl, const Config &c, int32_t batch, const double *ybu
 // (the allocation-free entry point) keeps everything on the caller's stream.
 constexpr int kPhaseStreams = 3;
 constexpr int kHeadTiles = 32;
+// without a head, the first chunk: the hardest instances in this many of the batch's own
+// tiles (9000-bus grid, 2,000 FP32-LU instances in tiles of eight: 40.2 ms per solve with 8
+// tiles, 40.6 with 16, 41.0 with 32)
+constexpr int kLeadTiles = 8;
 struct PhasePool {
     hipStream_t st[kPhaseStreams] = {};
     hipEvent_t start = nullptr, fin[kPhaseStreams] = {};
@@ -2378,7 +2382,7 @@ static hipError_t launch_phases_chunked(const HostPlan &h, const Config &c, cons
     // the head's workgroups hold their CUs throughout: a generation of the others fits the rest
     const int bgen = hcount > 0 ? std::max(1, (pp.cus - std::min(hgrid, pp.cus / 2)) * std::max(1, per_cu)) : gen;
     std::vector<int> cut{0};
-    if (order && !head) cut.push_back(std::min(btiles, kHeadTiles));
+    if (order && !head) cut.push_back(std::min(btiles, kLeadTiles));
     while (cut.back() < btiles) cut.push_back(std::min(btiles, cut.back() + bgen));
     const int nparts = (int)cut.size() - 1;
     // workers: 0 = the caller's stream, then the pool's streams; with a fused head the
