@@ -2313,9 +2313,10 @@ static hipError_t launch_phases_chunked(const HostPlan &h, const Config &c, cons
     Config ch;
     // The hardest instances run as the head (below), except in an FP32-LU flat-start batch
     // of at most one generation: there they are the first chunk of the batch's own tiles
-    // (9000-bus grid, 2,000 instances: 43.3 -> 41.5 ms per solve against the fused FP32 head,
+    // (9000-bus grid, 2,000 instances: 43.3 -> 40.3 ms per solve against the fused FP32 head,
     // which spills; in FP64 the head's four-instance tiles are the faster, 53.1 against
-    // 58.5 ms with the batch's eight, and with more generations the bulk sets the time)
+    // 58.5 ms with the batch's eight; with more generations the fused FP32 head stays ahead,
+    // 1350-bus 14.9 against 15.1-15.5 ms)
     const bool head = reorder && head_config(h, c, ch) && !(c.precision == PF_FP32_LU && nchunk <= 1 && !a.v_fb);
     char *head_ws = nullptr;
     if (reorder && iters > 1) {
@@ -2379,14 +2380,16 @@ static hipError_t launch_phases_chunked(const HostPlan &h, const Config &c, cons
             return e;
     }
     const int btiles = (a.batch - hcount + c.tile - 1) / c.tile;
-    // the head's workgroups hold their CUs throughout: a generation of the others fits the rest
+    // the head's workgroups hold their CUs (fused) or keep returning to them (per-phase): a
+    // generation of the others fits the rest (sized for every CU instead, the 9000-bus bulk
+    // slows the head: 51.8 -> 57.3 ms)
     const int bgen = hcount > 0 ? std::max(1, (pp.cus - std::min(hgrid, pp.cus / 2)) * std::max(1, per_cu)) : gen;
     std::vector<int> cut{0};
     if (order && !head) cut.push_back(std::min(btiles, kLeadTiles));
     while (cut.back() < btiles) cut.push_back(std::min(btiles, cut.back() + bgen));
     const int nparts = (int)cut.size() - 1;
-    // workers: 0 = the caller's stream, then the pool's streams; with a fused head the
-    // caller's stream holds only the head
+    // workers: 0 = the caller's stream, then the pool's streams; with a head the caller's
+    // stream holds only the head
     hipStream_t wk[kPhaseStreams + 1] = {user, pp.st[0], pp.st[1], pp.st[2]};
     const int w0 = hcount > 0 ? 1 : 0;
     const int nw = std::min(nparts + w0, kPhaseStreams + 1);
